@@ -1,0 +1,189 @@
+/*
+ * magfft -- FFT-based magnetization of type-II superconductors on one MI355X.
+ *
+ * C ABI of the method-of-lines right-hand side of Prigozhin & Sokolovsky,
+ * "FFT-based solution of 2D and 3D magnetization problems in type-II
+ * superconductivity":
+ *   dim 2 (thin film, Sec. 2): state g = stream function on nodes, eq. (2);
+ *         f(g, t) is the discretised iteration (11)-(12) with dh_z/dt in the
+ *         film from eq. (9).
+ *   dim 3 (bulk, Sec. 3):      state h = magnetic field on Yee-lattice edges;
+ *         f(h, t) is Faraday's law (14) with the power law (13) in Omega plus
+ *         iteration (18) with the Biot-Savart operator Phi of eq. (17).
+ * Everything is in the paper's dimensionless units (Sec. 2.3 and eq. (19)).
+ *
+ * Discretisation shared by both dimensions:
+ *   box D = [-L_a, L_a] per axis, periodic through the FFT (Sec. 2.2, 3.1);
+ *   n_a nodes at -L_a + i d_a, d_a = 2 L_a / n_a; cell i spans nodes i..i+1.
+ *   Arrays are row-major with x fastest: 2D [ny][nx], 3D [nz][ny][nx].
+ *   Derivatives are staggered finite differences; the film current sits on
+ *   edges, the bulk current j = curl h on faces (component c of h on the edge
+ *   half-shifted along axis c, component c of j on the face normal to c).
+ *   A node (2D) / edge (3D) is "inside" when all cells around it are
+ *   non-vacuum; every other node/edge is free space, where the iteration
+ *   determines the time derivative.
+ *
+ * Memory: every pointer argument marked "device" is caller-owned device memory
+ * (e.g. a contiguous torch tensor); the library never frees it or keeps it
+ * after the call returns.  The context owns all workspace (allocated by
+ * mag_set_grid / mag_set_domain and the first mag_step) and frees it in
+ * mag_destroy.  Pointers marked "host" are ordinary host memory.
+ *
+ * Streams: all device work is enqueued on the stream given to mag_create.
+ * Calls that return host scalars synchronise that stream before returning.
+ *
+ * Errors: negative return codes are hard errors.  MAG_E_ARG and MAG_E_STATE
+ * leave the context unchanged; MAG_E_HIP marks it unusable.  Positive codes
+ * are numerical statuses.  mag_last_error returns a description of the most
+ * recent failure.  A context is not thread-safe.
+ *
+ * Sizes: each n_a must be a power of two, 16 <= n_a <= 2048 (nz = 1 in 2D).
+ */
+#ifndef MAGFFT_H
+#define MAGFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mag_ctx mag_ctx;
+
+enum mag_status {
+  MAG_OK = 0,
+  MAG_NOT_CONVERGED = 1,   /* inner iteration did not reach its tolerance in max_inner steps */
+  MAG_STEP_UNDERFLOW = 2,  /* integrator step fell below 16 eps |t| */
+  MAG_E_ARG = -1,          /* invalid argument (size, pointer, value) */
+  MAG_E_STATE = -2,        /* call out of order (e.g. rhs before set_domain) */
+  MAG_E_HIP = -3,          /* HIP runtime error; the context must be destroyed */
+  MAG_E_NOMEM = -4,        /* device allocation failed */
+  MAG_E_NUMERIC = -5       /* non-finite value in the state or the result */
+};
+
+enum mag_precision {
+  MAG_FP64 = 0,  /* everything in double precision */
+  MAG_MIXED = 1  /* FFTs, Fourier multipliers and the power law in float; state,
+                    time stepping, step control and all iteration sums in double */
+};
+
+enum mag_field_kind {
+  MAG_FIELD_RAMP = 0,   /* h_e(t) = rate * t * dir            (Sec. 2.3: h_e = t) */
+  MAG_FIELD_SINE = 1,   /* h_e(t) = amp * sin(omega t) * dir  (Sec. 3.2 cube benchmark) */
+  MAG_FIELD_ROTATE = 2  /* h_e(t) = amp * (cos omega t, sin omega t, 0) */
+};
+
+/* Create a context for dim = 2 (film) or 3 (bulk) with the given precision.
+ * hip_stream: a hipStream_t (may be NULL for the default stream).
+ * Errors: MAG_E_ARG for a bad dim/precision/out pointer. */
+int mag_create(mag_ctx **out, int dim, int precision, void *hip_stream);
+
+/* Free the context and everything it owns.  NULL is ignored. */
+void mag_destroy(mag_ctx *ctx);
+
+/* Uniform grid on D = [-Lx,Lx] x [-Ly,Ly] (x [-Lz,Lz]) with nx x ny (x nz)
+ * nodes (Sec. 2.2 and 3.1).  nz must be 1 for dim 2.  Allocates the FFT and
+ * iteration workspace.  Errors: MAG_E_ARG (sizes not powers of two in
+ * [16, 2048], non-positive lengths), MAG_E_NOMEM. */
+int mag_set_grid(mag_ctx *ctx, int nx, int ny, int nz, double Lx, double Ly, double Lz);
+
+/* Material per cell, device uint8 array [nz][ny][nx] (nz = 1 in 2D):
+ * 0 free space, 1 superconductor (power law), 2 normal conductor with the
+ * resistivity rho_out (a filled hole, Sec. 2.2; a cut layer, Sec. 3.1).
+ * Copied; derives the inside/free-space classification and the pruning box.
+ * Errors: MAG_E_STATE before set_grid; MAG_E_ARG for codes > 2 or an empty
+ * sample. */
+int mag_set_domain(mag_ctx *ctx, const uint8_t *material);
+
+/* Power law (3)/(13): rho(|j|) = (e0 / jc)(|j| / jc)^(n-1) in superconducting
+ * cells, rho_out in normal cells.  jc per cell = jc0 * jc_map[cell] (device
+ * double array [nz][ny][nx], copied) or jc0 when jc_map is NULL; the jc of an
+ * edge/face is the mean of its two cells.  Errors: MAG_E_ARG for n < 1,
+ * jc0 <= 0, e0 <= 0, rho_out < 0, or a non-positive jc_map entry. */
+int mag_set_params(mag_ctx *ctx, const double *jc_map, double jc0, double n, double e0,
+                   double rho_out);
+
+/* Inner-iteration control.  lambda: relaxation of (12) (film only; Sec. 2.2
+ * uses 0.7).  inner_tol: stop when the mean free-space |gdot| (film, Sec. 2.3)
+ * or mean free-space |dh^{i+1} - dh^i| (bulk, Sec. 3.1) is below
+ * inner_tol * max(|dh_e/dt|, 1).  max_inner: iteration cap; exceeding it
+ * returns MAG_NOT_CONVERGED.  fixed_iters > 0: run exactly that many
+ * iterations without a stop test (used to compare implementations).
+ * Defaults: 0.7, 2e-4 (film) / 1e-4 (bulk), 100, 0. */
+int mag_set_solver(mag_ctx *ctx, double lambda, double inner_tol, int max_inner, int fixed_iters);
+
+/* Uniform applied field, see enum mag_field_kind.  dir: host double[3]
+ * (only the z component is used in 2D).  Default: ramp along z, rate 1. */
+int mag_set_field(mag_ctx *ctx, int kind, const double dir[3], double amp, double omega,
+                  double rate);
+
+/* One right-hand-side evaluation out = f(state, t).
+ * state, out: device double arrays of nx*ny (2D) or 3*nx*ny*nz (3D, component
+ *   planes [3][nz][ny][nx]); out must not alias state.
+ * n_inner (host, nullable): number of inner iterations used.
+ * The free-space part of the previous call's result is the first guess
+ * (warm start, Sec. 2.2); it is dropped after MAG_NOT_CONVERGED.
+ * Returns MAG_OK, MAG_NOT_CONVERGED (out undefined) or an error. */
+int mag_rhs(mag_ctx *ctx, const double *state, double t, double *out, int *n_inner);
+
+/* One adaptive Bogacki-Shampine 3(2) step attempt (the pair of Matlab's
+ * ode23 used in Sec. 2.2) from (state, *t) with step *dt.
+ * On acceptance state (device) and *t (host) advance and *accepted = 1; on
+ * rejection both stay and *accepted = 0.  *dt (host) receives the next step
+ * size either way.  Error norm max_i |err_i| / max(rtol max(|y_i|,|ynew_i|),
+ * atol); step factor min(5, max(0.2, 0.8 err^(-1/3))) after acceptance,
+ * max(0.2, 0.8 err^(-1/3)) after rejection, 1/2 when an inner iteration did
+ * not converge.  The first-same-as-last stage is reused while state and *t
+ * are unchanged since the previous accepted call. */
+int mag_step(mag_ctx *ctx, double *state, double *t, double *dt, double rtol, double atol,
+             int *accepted);
+
+/* Integrate from t0 to t1 with mag_step (first step 0.1 (t1 - t0) limited
+ * by 0.8 rtol^(1/3) / max_i(|f_i| / max(|y_i|, atol / rtol)); the last step
+ * lands on t1).  state: device, advanced in place.  obs (host, nullable):
+ * room for obs_cap records of 6 doubles per accepted step:
+ * t, dt, m_x, m_y, m_z, inner iterations of the step's last stage.
+ * n_steps (host): accepted steps.  Returns MAG_STEP_UNDERFLOW if the step
+ * collapses. */
+int mag_integrate(mag_ctx *ctx, double *state, double t0, double t1, double rtol, double atol,
+                  double *obs, int obs_cap, int *n_steps);
+
+/* Observables of a state (post-processing, Sec. 2.1 last formula):
+ * 2D: hz (device, nx*ny, nodes) = h_e + F^{-1}[|k|/2 F(g)]; j (device,
+ *     2*nx*ny: j_x on x-edges then j_y on y-edges, eq. (2)); m[0..2] (host)
+ *     = (0, 0, sum g dx dy).
+ * 3D: hz (device, nx*ny*nz) = z component of h on z-edges; j (device,
+ *     3*nx*ny*nz) = curl h on faces; m (host) = (1/2) sum r x j dV.
+ * hz and j may be NULL. */
+int mag_observe(mag_ctx *ctx, const double *state, double t, double *hz, double *j, double *m);
+
+/* Vector-Jacobian product of mag_rhs at (state, t): state_bar = (df/dstate)^T
+ * out_bar and jc_bar = (df/djc_map)^T out_bar (both device, same layouts as
+ * state and jc_map; jc_bar may be NULL).  The free-space iteration is
+ * differentiated as its converged fixed point (or, with fixed_iters, as
+ * exactly that many iterations); the warm start is a constant.  Overwrites
+ * state_bar and jc_bar. */
+int mag_rhs_vjp(mag_ctx *ctx, const double *state, double t, const double *out_bar,
+                double *state_bar, double *jc_bar);
+
+/* Forget the warm start: the next mag_rhs starts from dh_e/dt. */
+int mag_reset_warm_start(mag_ctx *ctx);
+
+/* Text of the most recent error or status (never NULL). */
+const char *mag_last_error(const mag_ctx *ctx);
+
+/* ---- instrumentation (timing of individual kernels, for benchmarks) ----
+ * mag_prof_enable(ctx, 1) records a pair of HIP events around every kernel
+ * launch on the context's stream; mag_prof_enable(ctx, 0) stops and clears.
+ * mag_prof_read sums the recorded durations of kernel `id` (synchronising the
+ * stream): *count launches, *total_ms milliseconds.  Launches that found the
+ * iteration already converged and returned at once are not recorded.
+ * mag_prof_kernel_name(id) names kernel id (NULL past the last id). */
+int mag_prof_enable(mag_ctx *ctx, int on);
+int mag_prof_read(mag_ctx *ctx, int id, int *count, double *total_ms);
+const char *mag_prof_kernel_name(int id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAGFFT_H */

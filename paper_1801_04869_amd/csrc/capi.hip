@@ -1,0 +1,709 @@
+// C ABI of the library (declared in include/magfft.h): context life cycle,
+// argument checks, twiddle tables, iteration finalizers, instrumentation and
+// the Bogacki-Shampine 3(2) driver (the explicit pair behind Matlab's ode23,
+// which the paper uses for the method of lines, Sec. 2.2).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "ctx.h"
+#include "kern_common.h"
+
+namespace mag {
+
+int set_error(mag_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+int hip_check(mag_ctx *c, hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    return set_error(c, MAG_E_NOMEM, "out of device memory in %s", what);
+  }
+  if (c) c->poisoned = true;
+  return set_error(c, MAG_E_HIP, "HIP error '%s' in %s", hipGetErrorString(e), what);
+}
+
+void field_h(const mag_ctx *c, double t, double h[3]) {
+  switch (c->fkind) {
+    case MAG_FIELD_RAMP:
+      for (int a = 0; a < 3; ++a) h[a] = c->fdir[a] * (c->frate * t);
+      break;
+    case MAG_FIELD_SINE:
+      for (int a = 0; a < 3; ++a) h[a] = c->fdir[a] * (c->famp * std::sin(c->fomega * t));
+      break;
+    default:
+      h[0] = c->famp * std::cos(c->fomega * t);
+      h[1] = c->famp * std::sin(c->fomega * t);
+      h[2] = 0.0;
+  }
+}
+
+void field_hdot(const mag_ctx *c, double t, double hd[3]) {
+  switch (c->fkind) {
+    case MAG_FIELD_RAMP:
+      for (int a = 0; a < 3; ++a) hd[a] = c->fdir[a] * c->frate;
+      break;
+    case MAG_FIELD_SINE:
+      for (int a = 0; a < 3; ++a) hd[a] = c->fdir[a] * (c->famp * c->fomega * std::cos(c->fomega * t));
+      break;
+    default: {
+      const double w = c->fomega;
+      hd[0] = c->famp * w * -std::sin(w * t);
+      hd[1] = c->famp * w * std::cos(w * t);
+      hd[2] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- instrumentation
+static hipEvent_t pool_get(mag_ctx *c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(mag_ctx *c, int kid, ProfRec *r) {
+  r->a = r->b = nullptr;
+  r->kid = kid;
+  r->iter = c->cur_iter;
+  if (!c->prof_on) return;
+  r->a = pool_get(c);
+  r->b = pool_get(c);
+  if (r->a) (void)hipEventRecord(r->a, c->stream);
+}
+
+void prof_end(mag_ctx *c, ProfRec *r) {
+  if (!c->prof_on || !r->a || !r->b) return;
+  (void)hipEventRecord(r->b, c->stream);
+  c->prof.push_back(*r);
+}
+
+// Called after an RHS: launches of iterations >= iters_done found `done` set
+// and returned at once; drop them (they are the newest records).
+void prof_drop_after(mag_ctx *c, int iters_done) {
+  if (!c->prof_on) return;
+  while (!c->prof.empty() && c->prof.back().iter >= iters_done) {
+    c->ev_pool.push_back(c->prof.back().a);
+    c->ev_pool.push_back(c->prof.back().b);
+    c->prof.pop_back();
+  }
+}
+
+static void prof_clear(mag_ctx *c) {
+  for (auto &r : c->prof) {
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof.clear();
+  for (int k = 0; k < K_COUNT; ++k) {
+    c->prof_ms[k] = 0;
+    c->prof_cnt[k] = 0;
+  }
+}
+
+// ---------------------------------------------------------------- finalizers
+namespace {
+
+__device__ __forceinline__ double fixed_order_sum(const double *__restrict__ part, int n, double *sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  return block_sum<256>(s, sh);
+}
+
+__global__ void __launch_bounds__(256) finalize_stop_k(const double *__restrict__ part, int n, IterState *it) {
+  if (it->done) return;
+  __shared__ double sh[256];
+  const double s = fixed_order_sum(part, n, sh);
+  if (threadIdx.x == 0) {
+    const double r = s * it->inv_nout;
+    it->r = r;
+    it->iters += 1;
+    if (!isfinite(r)) it->done = 2;
+    else if (it->fixed > 0) it->done = it->iters >= it->fixed ? 1 : 0;
+    else it->done = r < it->thr ? 1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) finalize_mean_k(const double *__restrict__ part, int n, IterState *it,
+                                                       int which) {
+  if (it->done) return;
+  __shared__ double sh[256];
+  const double s = fixed_order_sum(part, n, sh);
+  if (threadIdx.x == 0) {
+    if (which == 0) it->C = s * it->inv_nout;
+    else it->A = s * it->inv_nout;
+  }
+}
+
+// out = y + h * sum_i w_i k_i  (nk <= 3)
+__global__ void __launch_bounds__(256) rk_axpy_k(double *__restrict__ out, const double *__restrict__ y,
+                                                 const double *__restrict__ k0, const double *__restrict__ k1,
+                                                 const double *__restrict__ k2, double w0, double w1, double w2,
+                                                 int nk, double h, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = w0 * k0[i];
+  if (nk > 1) s += w1 * k1[i];
+  if (nk > 2) s += w2 * k2[i];
+  out[i] = y[i] + h * s;
+}
+
+// per-block max of |h sum e_i k_i| / max(rtol max(|y|,|ynew|), atol); non-finite -> inf
+__global__ void __launch_bounds__(256) rk_errnorm_k(const double *__restrict__ k1, const double *__restrict__ k2,
+                                                    const double *__restrict__ k3, const double *__restrict__ k4,
+                                                    double e1, double e2, double e3, double e4, double h,
+                                                    const double *__restrict__ y, const double *__restrict__ yn,
+                                                    double rtol, double atol, long long n,
+                                                    double *__restrict__ part) {
+  __shared__ double sh[256];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double err = h * (e1 * k1[i] + e2 * k2[i] + e3 * k3[i] + e4 * k4[i]);
+    const double sc = fmax(rtol * fmax(fabs(y[i]), fabs(yn[i])), atol);
+    v = fabs(err) / sc;
+    if (!isfinite(v)) v = INFINITY;
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// per-block max of |f| / max(|y|, thr)
+__global__ void __launch_bounds__(256) rk_ratio_k(const double *__restrict__ f, const double *__restrict__ y,
+                                                  double thr, long long n, double *__restrict__ part) {
+  __shared__ double sh[256];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    v = fabs(f[i]) / fmax(fabs(y[i]), thr);
+    if (!isfinite(v)) v = INFINITY;
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ void fill_twiddles(cx<T> *dst, const double *src, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = {(T)src[2 * i], (T)src[2 * i + 1]};
+}
+
+template <typename T>
+__global__ void scale_jc(const double *__restrict__ src, T *__restrict__ dst, double *__restrict__ d64,
+                         double jc0, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const double v = jc0 * src[i];
+    dst[i] = (T)v;
+    d64[i] = v;
+  }
+}
+
+}  // namespace
+
+int run_finalize_stop(mag_ctx *c, int nparts) {
+  ProfScope ps(c, K_FINALIZE);
+  hipLaunchKernelGGL(finalize_stop_k, dim3(1), dim3(256), 0, c->stream, c->d_part, nparts, c->d_it);
+  return MAG_OK;
+}
+
+int run_finalize_mean(mag_ctx *c, int nparts, int which) {
+  ProfScope ps(c, K_FINALIZE);
+  hipLaunchKernelGGL(finalize_mean_k, dim3(1), dim3(256), 0, c->stream, c->d_part, nparts, c->d_it, which);
+  return MAG_OK;
+}
+
+static int ensure_red(mag_ctx *c, long long n) {
+  const int nb = (int)((n + 255) / 256);
+  if (c->nred < nb) {
+    if (c->d_red) (void)hipFree(c->d_red);
+    c->d_red = nullptr;
+    MAG_HIP(c, hipMalloc(&c->d_red, (size_t)nb * sizeof(double)));
+    c->nred = nb;
+  }
+  return MAG_OK;
+}
+
+static int host_max(mag_ctx *c, int nb, double *out) {
+  std::vector<double> v(nb);
+  MAG_HIP(c, hipMemcpyAsync(v.data(), c->d_red, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  double m = 0.0;
+  for (double x : v) m = std::max(m, x);
+  *out = m;
+  return MAG_OK;
+}
+
+}  // namespace mag
+
+using namespace mag;
+
+// ==================================================================== C ABI
+extern "C" {
+
+static const char *kNames[K_COUNT] = {
+    "film_stencil", "film_rows_fwd_h", "film_cols", "film_rows_inv_g", "film_rows_fwd_g", "film_rows_inv_upd",
+    "bulk_curl_box", "bulk_efield_box", "bulk_hdot_in", "bulk_x_fwd", "bulk_y_fwd", "bulk_z_phi",
+    "bulk_y_inv", "bulk_x_inv", "finalize", "misc", "rk", "vjp"};
+
+static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+static void free_all(mag_ctx *c) {
+  void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
+                  c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_adj};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  c->d_mat = c->d_flags = nullptr;
+  c->d_jc = c->d_H = c->d_G = c->d_S = c->d_box = c->d_tw = c->d_adj = nullptr;
+  c->d_jc64 = c->d_part = c->d_sym = c->d_rk = c->d_red = nullptr;
+  c->d_it = nullptr;
+  c->nred = 0;
+  c->adj_bytes = 0;
+}
+
+int mag_create(mag_ctx **out, int dim, int precision, void *hip_stream) {
+  if (!out) return MAG_E_ARG;
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return MAG_E_ARG;
+  if (precision != MAG_FP64 && precision != MAG_MIXED) return MAG_E_ARG;
+  mag_ctx *c = new (std::nothrow) mag_ctx();
+  if (!c) return MAG_E_NOMEM;
+  c->dim = dim;
+  c->prec = precision;
+  c->ncomp = dim == 3 ? 3 : 1;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (dim == 3) c->tol = 1e-4;
+  if (hipHostMalloc(&c->h_it, sizeof(IterState)) != hipSuccess) {
+    delete c;
+    return MAG_E_HIP;
+  }
+  if (hipMalloc(&c->d_it, sizeof(IterState)) != hipSuccess) {
+    (void)hipHostFree(c->h_it);
+    delete c;
+    return MAG_E_NOMEM;
+  }
+  *out = c;
+  return MAG_OK;
+}
+
+void mag_destroy(mag_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  prof_clear(c);
+  for (hipEvent_t e : c->ev_pool)
+    if (e) (void)hipEventDestroy(e);
+  free_all(c);
+  if (c->h_it) (void)hipHostFree(c->h_it);
+  delete c;
+}
+
+const char *mag_last_error(const mag_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+#define CHECK_CTX(c)                                                     \
+  do {                                                                   \
+    if (!(c)) return MAG_E_ARG;                                          \
+    if ((c)->poisoned) return set_error(c, MAG_E_HIP, "context unusable after a HIP error"); \
+  } while (0)
+
+int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, double Lz) {
+  CHECK_CTX(c);
+  if (!pow2_in(nx, 16, 2048) || !pow2_in(ny, 16, 2048))
+    return set_error(c, MAG_E_ARG, "nx, ny must be powers of two in [16, 2048]");
+  if (c->dim == 2 && nz != 1) return set_error(c, MAG_E_ARG, "nz must be 1 for a film");
+  if (c->dim == 3 && !pow2_in(nz, 16, 2048)) return set_error(c, MAG_E_ARG, "nz must be a power of two in [16, 2048]");
+  if (!(Lx > 0) || !(Ly > 0) || (c->dim == 3 && !(Lz > 0))) return set_error(c, MAG_E_ARG, "box half-lengths must be positive");
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  IterState *keep_it = c->d_it;
+  c->d_it = nullptr;
+  free_all(c);
+  c->d_it = keep_it;
+  c->grid_set = c->domain_set = false;
+  c->has_jc_map = false;
+  c->n[0] = nx;
+  c->n[1] = ny;
+  c->n[2] = nz;
+  c->L[0] = Lx;
+  c->L[1] = Ly;
+  c->L[2] = c->dim == 3 ? Lz : 1.0;
+  for (int a = 0; a < 3; ++a) c->d[a] = 2.0 * c->L[a] / c->n[a];
+  c->nnode = (long long)nx * ny * nz;
+  c->kx = nx / 2 + 1;
+  c->nspec = (long long)c->kx * ny * nz;
+  c->warm_valid = false;
+  c->fsal_valid = false;
+  c->last_iters = 1;
+  int rc = c->dim == 3 ? bulk_alloc(c) : film_alloc(c);
+  if (rc) return rc;
+  // twiddles exp(-2 pi i m / n): x half length, y, z, x full length
+  std::vector<double> tw;
+  auto add = [&](int n, int slot) {
+    c->tw_off[slot] = (long long)tw.size() / 2;
+    for (int m = 0; m < n; ++m) {
+      const double a = -2.0 * M_PI * (double)m / (double)n;
+      tw.push_back(std::cos(a));
+      tw.push_back(std::sin(a));
+    }
+  };
+  add(nx / 2, 0);
+  add(ny, 1);
+  add(c->dim == 3 ? nz : 1, 2);
+  add(nx, 3);
+  const long long ntw = (long long)tw.size() / 2;
+  const size_t ts = c->prec == MAG_FP64 ? 8 : 4;
+  double *tmp = nullptr;
+  MAG_HIP(c, hipMalloc(&c->d_tw, ntw * 2 * ts));
+  MAG_HIP(c, hipMalloc(&tmp, tw.size() * sizeof(double)));
+  MAG_HIP(c, hipMemcpy(tmp, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (c->prec == MAG_FP64)
+    hipLaunchKernelGGL((fill_twiddles<double>), dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<cx<double> *>(c->d_tw), tmp, ntw);
+  else
+    hipLaunchKernelGGL((fill_twiddles<float>), dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<cx<float> *>(c->d_tw), tmp, ntw);
+  MAG_HIP(c, hipGetLastError());
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  MAG_HIP(c, hipFree(tmp));
+  // per-cell jc (uniform until set_params gives a map)
+  MAG_HIP(c, hipMalloc(&c->d_jc, c->nnode * ts));
+  MAG_HIP(c, hipMalloc(&c->d_jc64, c->nnode * sizeof(double)));
+  c->grid_set = true;
+  return MAG_OK;
+}
+
+int mag_set_domain(mag_ctx *c, const uint8_t *material) {
+  CHECK_CTX(c);
+  if (!c->grid_set) return set_error(c, MAG_E_STATE, "mag_set_domain before mag_set_grid");
+  if (!material) return set_error(c, MAG_E_ARG, "material is NULL");
+  std::vector<uint8_t> m(c->nnode);
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  MAG_HIP(c, hipMemcpy(m.data(), material, c->nnode, hipMemcpyDefault));
+  for (uint8_t v : m)
+    if (v > 2) return set_error(c, MAG_E_ARG, "material codes must be 0, 1 or 2");
+  c->h_mat.swap(m);
+  int rc = c->dim == 3 ? bulk_domain(c) : film_domain(c);
+  if (rc) {
+    c->domain_set = false;
+    return rc;
+  }
+  c->domain_set = true;
+  c->fsal_valid = false;
+  return MAG_OK;
+}
+
+int mag_set_params(mag_ctx *c, const double *jc_map, double jc0, double n, double e0, double rho_out) {
+  CHECK_CTX(c);
+  if (!c->grid_set) return set_error(c, MAG_E_STATE, "mag_set_params before mag_set_grid");
+  if (!(n >= 1.0) || !(jc0 > 0) || !(e0 > 0) || !(rho_out >= 0) || !std::isfinite(n) || !std::isfinite(jc0))
+    return set_error(c, MAG_E_ARG, "need n >= 1, jc0 > 0, e0 > 0, rho_out >= 0");
+  if (jc_map) {
+    std::vector<double> h(c->nnode);
+    MAG_HIP(c, hipStreamSynchronize(c->stream));
+    MAG_HIP(c, hipMemcpy(h.data(), jc_map, c->nnode * sizeof(double), hipMemcpyDefault));
+    for (double v : h)
+      if (!(v > 0) || !std::isfinite(v)) return set_error(c, MAG_E_ARG, "jc_map entries must be positive and finite");
+    double *tmp = nullptr;
+    MAG_HIP(c, hipMalloc(&tmp, c->nnode * sizeof(double)));
+    MAG_HIP(c, hipMemcpy(tmp, h.data(), c->nnode * sizeof(double), hipMemcpyHostToDevice));
+    const unsigned nb = (unsigned)((c->nnode + 255) / 256);
+    if (c->prec == MAG_FP64)
+      hipLaunchKernelGGL((scale_jc<double>), dim3(nb), dim3(256), 0, c->stream, tmp,
+                         reinterpret_cast<double *>(c->d_jc), c->d_jc64, jc0, c->nnode);
+    else
+      hipLaunchKernelGGL((scale_jc<float>), dim3(nb), dim3(256), 0, c->stream, tmp,
+                         reinterpret_cast<float *>(c->d_jc), c->d_jc64, jc0, c->nnode);
+    MAG_HIP(c, hipGetLastError());
+    MAG_HIP(c, hipStreamSynchronize(c->stream));
+    MAG_HIP(c, hipFree(tmp));
+  }
+  c->has_jc_map = jc_map != nullptr;
+  c->jc0 = jc0;
+  c->nexp = n;
+  c->e0 = e0;
+  c->rho_out = rho_out;
+  c->fsal_valid = false;
+  return MAG_OK;
+}
+
+int mag_set_solver(mag_ctx *c, double lambda, double inner_tol, int max_inner, int fixed_iters) {
+  CHECK_CTX(c);
+  if (!(lambda > 0) || !(inner_tol >= 0) || max_inner < 1 || fixed_iters < 0 || max_inner > 100000 ||
+      fixed_iters > 100000)
+    return set_error(c, MAG_E_ARG, "need lambda > 0, inner_tol >= 0, 1 <= max_inner, fixed_iters >= 0");
+  c->lambda = lambda;
+  c->tol = inner_tol;
+  c->max_inner = max_inner;
+  c->fixed_iters = fixed_iters;
+  c->fsal_valid = false;
+  return MAG_OK;
+}
+
+int mag_set_field(mag_ctx *c, int kind, const double dir[3], double amp, double omega, double rate) {
+  CHECK_CTX(c);
+  if (kind < 0 || kind > 2) return set_error(c, MAG_E_ARG, "unknown field kind");
+  if ((kind != MAG_FIELD_ROTATE) && !dir) return set_error(c, MAG_E_ARG, "dir is NULL");
+  c->fkind = kind;
+  if (dir)
+    for (int a = 0; a < 3; ++a) c->fdir[a] = dir[a];
+  c->famp = amp;
+  c->fomega = omega;
+  c->frate = rate;
+  c->fsal_valid = false;
+  return MAG_OK;
+}
+
+static int ready(mag_ctx *c) {
+  if (!c->grid_set) return set_error(c, MAG_E_STATE, "grid not set");
+  if (!c->domain_set) return set_error(c, MAG_E_STATE, "domain not set");
+  return MAG_OK;
+}
+
+static int rhs_impl(mag_ctx *c, const double *state, double t, double *out, int *n_inner) {
+  return c->dim == 3 ? bulk_rhs(c, state, t, out, n_inner) : film_rhs(c, state, t, out, n_inner);
+}
+
+int mag_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state || !out) return set_error(c, MAG_E_ARG, "state/out is NULL");
+  if (state == out) return set_error(c, MAG_E_ARG, "out must not alias state");
+  if (!std::isfinite(t)) return set_error(c, MAG_E_ARG, "t is not finite");
+  c->fsal_valid = false;
+  return rhs_impl(c, state, t, out, n_inner);
+}
+
+int mag_reset_warm_start(mag_ctx *c) {
+  CHECK_CTX(c);
+  c->warm_valid = false;
+  c->last_iters = 1;
+  return MAG_OK;
+}
+
+// ---------------------------------------------------------------- time stepping
+static const double kRkC2 = 0.5, kRkC3 = 0.75, kA21 = 0.5, kA32 = 0.75;
+static const double kB1 = 2.0 / 9.0, kB2 = 1.0 / 3.0, kB3 = 4.0 / 9.0;
+static const double kE1 = -5.0 / 72.0, kE2 = 1.0 / 12.0, kE3 = 1.0 / 9.0, kE4 = -1.0 / 8.0;
+
+static long long state_len(const mag_ctx *c) { return c->nnode * c->ncomp; }
+
+static int ensure_rk(mag_ctx *c) {
+  if (c->d_rk) return MAG_OK;
+  MAG_HIP(c, hipMalloc(&c->d_rk, 6 * state_len(c) * sizeof(double)));
+  return MAG_OK;
+}
+
+static double *rk_buf(mag_ctx *c, int i) { return c->d_rk + (long long)i * state_len(c); }
+
+// buffers: 0..3 = k1..k4 (k1/k4 roles swap after each accepted step), 4 = ytmp, 5 = ynew
+
+static int launch_axpy(mag_ctx *c, double *out, const double *y, const double *k0, const double *k1,
+                       const double *k2, double w0, double w1, double w2, int nk, double h) {
+  const long long n = state_len(c);
+  ProfScope ps(c, K_RK);
+  hipLaunchKernelGGL(rk_axpy_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, out, y, k0,
+                     k1 ? k1 : k0, k2 ? k2 : k0, w0, w1, w2, nk, h, n);
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
+static int step_impl(mag_ctx *c, double *state, double *t, double *dt, double rtol, double atol, int *accepted) {
+  int rc = ensure_rk(c);
+  if (rc) return rc;
+  const long long n = state_len(c);
+  double *k1 = rk_buf(c, c->rk_k1), *k4 = rk_buf(c, c->rk_k4);
+  double *k2 = rk_buf(c, 1), *k3 = rk_buf(c, 2), *yt = rk_buf(c, 4), *yn = rk_buf(c, 5);
+  const double h = *dt;
+  *accepted = 0;
+  if (!(c->fsal_valid && c->fsal_state == state && c->fsal_t == *t)) {
+    rc = rhs_impl(c, state, *t, k1, nullptr);
+    if (rc != MAG_OK) return rc;
+    c->fsal_valid = true;
+    c->fsal_state = state;
+    c->fsal_t = *t;
+  }
+  auto failed = [&](int st) { return st == MAG_NOT_CONVERGED || st == MAG_E_NUMERIC; };
+  if ((rc = launch_axpy(c, yt, state, k1, nullptr, nullptr, 1.0, 0, 0, 1, kA21 * h))) return rc;
+  rc = rhs_impl(c, yt, *t + kRkC2 * h, k2, nullptr);
+  if (failed(rc)) {
+    *dt = 0.5 * h;
+    return MAG_OK;
+  }
+  if (rc) return rc;
+  if ((rc = launch_axpy(c, yt, state, k2, nullptr, nullptr, 1.0, 0, 0, 1, kA32 * h))) return rc;
+  rc = rhs_impl(c, yt, *t + kRkC3 * h, k3, nullptr);
+  if (failed(rc)) {
+    *dt = 0.5 * h;
+    return MAG_OK;
+  }
+  if (rc) return rc;
+  if ((rc = launch_axpy(c, yn, state, k1, k2, k3, kB1, kB2, kB3, 3, h))) return rc;
+  rc = rhs_impl(c, yn, *t + h, k4, nullptr);
+  if (failed(rc)) {
+    *dt = 0.5 * h;
+    return MAG_OK;
+  }
+  if (rc) return rc;
+  if ((rc = ensure_red(c, n))) return rc;
+  const int nb = (int)((n + 255) / 256);
+  {
+    ProfScope ps(c, K_RK);
+    hipLaunchKernelGGL(rk_errnorm_k, dim3(nb), dim3(256), 0, c->stream, k1, k2, k3, k4, kE1, kE2, kE3, kE4, h,
+                       state, yn, rtol, atol, n, c->d_red);
+  }
+  MAG_HIP(c, hipGetLastError());
+  double en = 0.0;
+  if ((rc = host_max(c, nb, &en))) return rc;
+  if (en <= 1.0) {
+    MAG_HIP(c, hipMemcpyAsync(state, yn, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    std::swap(c->rk_k1, c->rk_k4);
+    *t = *t + h;
+    c->fsal_valid = true;
+    c->fsal_state = state;
+    c->fsal_t = *t;
+    const double fac = en == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.8 * std::pow(en, -1.0 / 3.0)));
+    *dt = h * fac;
+    *accepted = 1;
+  } else {
+    const double fac = std::max(0.2, 0.8 * std::pow(en, -1.0 / 3.0));
+    *dt = h * fac;
+  }
+  return MAG_OK;
+}
+
+int mag_step(mag_ctx *c, double *state, double *t, double *dt, double rtol, double atol, int *accepted) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state || !t || !dt || !accepted) return set_error(c, MAG_E_ARG, "NULL argument");
+  if (!(*dt > 0) || !std::isfinite(*t) || !(rtol > 0) || !(atol > 0))
+    return set_error(c, MAG_E_ARG, "need dt > 0, rtol > 0, atol > 0");
+  return step_impl(c, state, t, dt, rtol, atol, accepted);
+}
+
+int mag_integrate(mag_ctx *c, double *state, double t0, double t1, double rtol, double atol, double *obs,
+                  int obs_cap, int *n_steps) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state || !n_steps) return set_error(c, MAG_E_ARG, "NULL argument");
+  if (!(t1 > t0) || !(rtol > 0) || !(atol > 0)) return set_error(c, MAG_E_ARG, "need t1 > t0, rtol > 0, atol > 0");
+  if ((rc = ensure_rk(c))) return rc;
+  *n_steps = 0;
+  const long long n = state_len(c);
+  double t = t0;
+  int it0 = 0;
+  rc = rhs_impl(c, state, t, rk_buf(c, c->rk_k1), &it0);
+  if (rc) return rc;
+  c->fsal_valid = true;
+  c->fsal_state = state;
+  c->fsal_t = t;
+  if ((rc = ensure_red(c, n))) return rc;
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(rk_ratio_k, dim3(nb), dim3(256), 0, c->stream, rk_buf(c, c->rk_k1), state, atol / rtol, n, c->d_red);
+  MAG_HIP(c, hipGetLastError());
+  double mx = 0.0;
+  if ((rc = host_max(c, nb, &mx))) return rc;
+  const double rh = mx / (0.8 * std::cbrt(rtol));
+  double h = 0.1 * std::fabs(t1 - t0);
+  if (rh * h > 1.0) h = 1.0 / rh;
+  long long attempts = 0;
+  while (t < t1 && attempts < 10000000LL) {
+    if (1.1 * h >= t1 - t) h = t1 - t;
+    if (h <= 16.0 * 2.220446049250313e-16 * std::max(std::fabs(t), 1.0))
+      return set_error(c, MAG_STEP_UNDERFLOW, "step size underflow at t = %g", t);
+    int acc = 0;
+    const double hstep = h;
+    rc = step_impl(c, state, &t, &h, rtol, atol, &acc);
+    ++attempts;
+    if (rc) return rc;
+    if (acc) {
+      if (obs && *n_steps < obs_cap) {
+        double m[3] = {0, 0, 0};
+        rc = c->dim == 3 ? bulk_observe(c, state, t, nullptr, nullptr, m) : film_observe(c, state, t, nullptr, nullptr, m);
+        if (rc) return rc;
+        double *o = obs + 6LL * (*n_steps);
+        o[0] = t;
+        o[1] = hstep;
+        o[2] = m[0];
+        o[3] = m[1];
+        o[4] = m[2];
+        o[5] = (double)c->last_iters;
+      }
+      ++*n_steps;
+    }
+  }
+  return MAG_OK;
+}
+
+int mag_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state || !m) return set_error(c, MAG_E_ARG, "state/m is NULL");
+  return c->dim == 3 ? bulk_observe(c, state, t, hz, j, m) : film_observe(c, state, t, hz, j, m);
+}
+
+int mag_rhs_vjp(mag_ctx *c, const double *state, double t, const double *out_bar, double *state_bar,
+                double *jc_bar) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state || !out_bar || !state_bar) return set_error(c, MAG_E_ARG, "NULL argument");
+  c->fsal_valid = false;
+  return c->dim == 3 ? bulk_rhs_vjp(c, state, t, out_bar, state_bar, jc_bar)
+                     : film_rhs_vjp(c, state, t, out_bar, state_bar, jc_bar);
+}
+
+int mag_prof_enable(mag_ctx *c, int on) {
+  if (!c) return MAG_E_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  prof_clear(c);
+  c->prof_on = on != 0;
+  return MAG_OK;
+}
+
+int mag_prof_read(mag_ctx *c, int id, int *count, double *total_ms) {
+  if (!c || id < 0 || id >= K_COUNT || !count || !total_ms) return MAG_E_ARG;
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  int cnt = 0;
+  double tot = 0.0;
+  for (auto &r : c->prof) {
+    if (r.kid != id) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      tot += ms;
+      ++cnt;
+    }
+  }
+  *count = cnt;
+  *total_ms = tot;
+  return MAG_OK;
+}
+
+const char *mag_prof_kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kNames[id] : nullptr; }
+
+}  // extern "C"

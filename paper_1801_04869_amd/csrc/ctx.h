@@ -1,0 +1,183 @@
+// Internal context of the magfft library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/magfft.h"
+
+namespace mag {
+
+// Per-call iteration state kept in device memory.  Kernels of an iteration
+// read `done` and return at once when it is set, so a block of iterations can
+// be enqueued without host round trips.
+struct IterState {
+  int done;       // 1 once the stop test passed (or the fixed count is reached)
+  int iters;      // inner iterations performed (film: evaluations of (11))
+  int fixed;      // fixed iteration count, 0 = stop test
+  int pad;
+  double thr;     // stop threshold tol * max(|dh_e/dt|, 1)
+  double inv_nout;
+  double C;       // film: free-space mean of G, eq. (11)
+  double A;       // film: pending constant shift of (10)/(12)
+  double r;       // last residual
+  double sum0;    // scratch
+};
+
+// Kernel identifiers for the instrumentation.
+enum KernelId {
+  K_FILM_STENCIL = 0,
+  K_FILM_ROWS_FWD_H,
+  K_FILM_COLS,
+  K_FILM_ROWS_INV_G,
+  K_FILM_ROWS_FWD_G,
+  K_FILM_ROWS_INV_UPD,
+  K_BULK_CURL,
+  K_BULK_EFIELD,
+  K_BULK_HDOT_IN,
+  K_BULK_X_FWD,
+  K_BULK_Y_FWD,
+  K_BULK_Z_PHI,
+  K_BULK_Y_INV,
+  K_BULK_X_INV_UPD,
+  K_FINALIZE,
+  K_MISC,
+  K_RK,
+  K_VJP,
+  K_COUNT
+};
+
+struct ProfRec {
+  hipEvent_t a, b;
+  int kid;
+  int iter;   // inner iteration index, -1 for per-call kernels
+};
+
+}  // namespace mag
+
+struct mag_ctx {
+  int dim = 0;
+  int prec = 0;
+  hipStream_t stream = nullptr;
+  bool poisoned = false;
+  std::string err;
+
+  // grid
+  bool grid_set = false, domain_set = false;
+  int n[3] = {1, 1, 1};          // nx, ny, nz
+  double L[3] = {1, 1, 1}, d[3] = {1, 1, 1};
+  long long nnode = 0;            // nx*ny*nz
+  int kx = 0;                     // nx/2 + 1
+  long long nspec = 0;            // kx*ny*nz complex per component
+  int ncomp = 1;                  // 1 (film) or 3 (bulk)
+
+  // domain
+  std::vector<uint8_t> h_mat;     // host copy of the material
+  uint8_t *d_mat = nullptr;
+  uint8_t *d_flags = nullptr;     // 2D: bit0 inside node; 3D: bits 0-2 inside faces, 3-5 inside edges
+  long long nout = 0;             // number of free-space unknowns (nodes / edges)
+  int box0[3] = {0, 0, 0}, box1[3] = {0, 0, 0};   // node box holding every inside face/edge/node
+
+  // parameters
+  double jc0 = 1, nexp = 19, e0 = 1, rho_out = 1;
+  bool has_jc_map = false;
+  void *d_jc = nullptr;           // per-cell jc (precision type)
+  double *d_jc64 = nullptr;       // per-cell jc, double (VJP)
+  double lambda = 0.7, tol = 2e-4;
+  int max_inner = 100, fixed_iters = 0;
+
+  // field
+  int fkind = 0;
+  double fdir[3] = {0, 0, 1}, famp = 1, fomega = 1, frate = 1;
+
+  // workspace
+  void *d_H = nullptr;            // iterate: film dh_z/dt on nodes; bulk dh/dt on edges (precision type)
+  void *d_G = nullptr;            // film: G of (11) (precision type)
+  void *d_S = nullptr;            // half spectrum, ncomp planes of kx*ny*nz complex
+  void *d_box = nullptr;          // bulk stencil scratch: j then e on the pruning box (precision type)
+  long long boxvol = 0;
+  int boxn[3] = {0, 0, 0};
+  double *d_part = nullptr;       // per-block partial sums
+  int npart = 0;
+  mag::IterState *d_it = nullptr;
+  mag::IterState *h_it = nullptr; // pinned
+  void *d_tw = nullptr;           // twiddle tables (precision type)
+  long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
+  double *d_sym = nullptr;        // per-axis symbol tables (double)
+  long long sym_off[8] = {0};
+  bool warm_valid = false;
+  int last_iters = 1;
+
+  // time stepping
+  double *d_rk = nullptr;         // k1..k4, ytmp, ynew
+  int rk_k1 = 0, rk_k4 = 3;       // which buffers currently hold k1 and k4
+  bool fsal_valid = false;
+  const double *fsal_state = nullptr;
+  double fsal_t = 0;
+  double *d_red = nullptr;        // reduction scratch for step control
+  int nred = 0;
+
+  // adjoint scratch
+  void *d_adj = nullptr;
+  long long adj_bytes = 0;
+
+  // instrumentation
+  bool prof_on = false;
+  std::vector<mag::ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
+  int cur_iter = -1;
+  double prof_ms[mag::K_COUNT] = {0};
+  int prof_cnt[mag::K_COUNT] = {0};
+};
+
+namespace mag {
+
+int set_error(mag_ctx *c, int code, const char *fmt, ...);
+int hip_check(mag_ctx *c, hipError_t e, const char *what);
+
+#define MAG_HIP(ctx, expr)                                  \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return ::mag::hip_check(ctx, e_, #expr); \
+  } while (0)
+
+// instrumentation helpers
+void prof_begin(mag_ctx *c, int kid, ProfRec *r);
+void prof_end(mag_ctx *c, ProfRec *r);
+void prof_drop_after(mag_ctx *c, int iters_done);
+
+// Scoped launch timing: records events around the kernel when profiling is on.
+struct ProfScope {
+  mag_ctx *c;
+  ProfRec r;
+  ProfScope(mag_ctx *c_, int kid) : c(c_) { prof_begin(c, kid, &r); }
+  ~ProfScope() { prof_end(c, &r); }
+};
+
+// dimension-specific drivers
+int film_alloc(mag_ctx *c);
+int film_domain(mag_ctx *c);
+int film_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner);
+int film_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m);
+int film_rhs_vjp(mag_ctx *c, const double *state, double t, const double *out_bar,
+                 double *state_bar, double *jc_bar);
+int bulk_alloc(mag_ctx *c);
+int bulk_domain(mag_ctx *c);
+int bulk_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner);
+int bulk_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m);
+int bulk_rhs_vjp(mag_ctx *c, const double *state, double t, const double *out_bar,
+                 double *state_bar, double *jc_bar);
+
+// applied field
+void field_h(const mag_ctx *c, double t, double h[3]);
+void field_hdot(const mag_ctx *c, double t, double hd[3]);
+
+// shared launches (capi.hip, bulk.hip)
+int run_finalize_stop(mag_ctx *c, int nparts);
+int run_finalize_mean(mag_ctx *c, int nparts, int which);
+int run_to_double(mag_ctx *c, const void *src, double *dst, long long n);
+
+}  // namespace mag

@@ -1,0 +1,205 @@
+// Device building blocks of the pencil FFTs (gfx950, wave64).
+//
+// A pencil of length N (a power of two, 8..4096) is spread over TT = N / RMAX
+// threads; thread j holds the RMAX values x[j + rho * TT] in registers.  The
+// transform is a mixed-radix Stockham decimation-in-time: stage s combines
+// sub-transforms of length Ns (product of the earlier radices) with radix R_s.
+// Between stages the data goes through LDS; the first stage reads the
+// register pattern above straight from global memory and the last stage
+// leaves X[j + rho * TT] in registers, so a two-stage pencil costs one LDS
+// exchange.  In-register DFTs of size 2..16 are unrolled radix-2 butterflies
+// with compile-time twiddles; inter-stage twiddles come from a table of
+// exp(-2 pi i m / N) built on the host in double precision.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+namespace mag {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------------- compile-time loops
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev(int i, int n) {
+  int r = 0;
+  for (int b = 1; b < n; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// cos and sin of 2 pi m / 16
+constexpr double kC1 = 0.92387953251128674;   // cos(pi/8)
+constexpr double kC2 = 0.70710678118654752;   // cos(pi/4)
+constexpr double kC3 = 0.38268343236508978;   // cos(3pi/8)
+constexpr double kCos16[16] = {1, kC1, kC2, kC3, 0, -kC3, -kC2, -kC1, -1, -kC1, -kC2, -kC3, 0, kC3, kC2, kC1};
+constexpr double kSin16[16] = {0, kC3, kC2, kC1, 1, kC1, kC2, kC3, 0, -kC3, -kC2, -kC1, -1, -kC1, -kC2, -kC3};
+
+// a * exp(DIR * 2 pi i M / R), M a compile-time integer; DIR = -1 forward, +1 inverse.
+template <int R, int DIR, int M, typename T>
+__device__ __forceinline__ cx<T> rot(cx<T> a) {
+  constexpr int m = ((M % R) + R) % R;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (2 * m == R) {
+    return {-a.x, -a.y};
+  } else if constexpr (4 * m == R) {
+    if constexpr (DIR < 0) return {a.y, -a.x};   // * (-i)
+    else return {-a.y, a.x};                     // * (+i)
+  } else if constexpr (4 * m == 3 * R) {
+    if constexpr (DIR < 0) return {-a.y, a.x};
+    else return {a.y, -a.x};
+  } else {
+    constexpr double c = kCos16[m * (16 / R)];
+    constexpr double s = DIR * kSin16[m * (16 / R)];
+    const T wr = (T)c, wi = (T)s;
+    return {a.x * wr - a.y * wi, a.x * wi + a.y * wr};
+  }
+}
+
+// In-register DFT of size R (2, 4, 8 or 16), natural order in and out.
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 1) {
+    return;
+  } else {
+    static_for<0, ilog2(R)>([&](auto st) {
+      constexpr int span = R >> (decltype(st)::value + 1);
+      static_for<0, R / (2 * span)>([&](auto bi) {
+        constexpr int base = decltype(bi)::value * 2 * span;
+        static_for<0, span>([&](auto kk) {
+          constexpr int k = decltype(kk)::value;
+          const cx<T> a = v[base + k], b = v[base + k + span];
+          v[base + k] = a + b;
+          v[base + k + span] = rot<R, DIR, k*(R / (2 * span))>(a - b);
+        });
+      });
+    });
+    static_for<0, R>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      constexpr int j = bitrev(i, R);
+      if constexpr (j > i) {
+        const cx<T> t = v[i];
+        v[i] = v[j];
+        v[j] = t;
+      }
+    });
+  }
+}
+
+// ---------------------------------------------------------------- plans
+template <int N>
+struct Plan;
+#define MAG_PLAN(N_, S_, RMAX_, R0, R1, R2)                  \
+  template <>                                                \
+  struct Plan<N_> {                                          \
+    static constexpr int S = S_, RMAX = RMAX_;               \
+    static constexpr int R[3] = {R0, R1, R2};                \
+    static constexpr int TT = N_ / RMAX_;                    \
+  };
+MAG_PLAN(8, 1, 8, 8, 1, 1)
+MAG_PLAN(16, 1, 16, 16, 1, 1)
+MAG_PLAN(32, 2, 8, 8, 4, 1)
+MAG_PLAN(64, 2, 8, 8, 8, 1)
+MAG_PLAN(128, 2, 16, 16, 8, 1)
+MAG_PLAN(256, 2, 16, 16, 16, 1)
+MAG_PLAN(512, 3, 8, 8, 8, 8)
+MAG_PLAN(1024, 3, 16, 16, 16, 4)
+MAG_PLAN(2048, 3, 16, 16, 16, 8)
+MAG_PLAN(4096, 3, 16, 16, 16, 16)
+#undef MAG_PLAN
+
+template <int N, int s>
+constexpr int plan_ns() {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= Plan<N>::R[i];
+  return ns;
+}
+
+// One pencil transform.  v[RMAX] holds x[j + rho*TT] on entry and X[j + rho*TT]
+// on exit.  lre/lim: this pencil's LDS scratch (real and imaginary planes),
+// element i at offset lidx(i).  tw: exp(-2 pi i m / N), m = 0..N-1.
+// Every thread of the block must call this (it contains barriers).
+template <int N, int DIR, typename T, typename LIdx>
+__device__ __forceinline__ void pencil_fft(cx<T>* v, int j, T* lre, T* lim, LIdx lidx,
+                                           const cx<T>* __restrict__ tw) {
+  using P = Plan<N>;
+  constexpr int RMAX = P::RMAX, TT = P::TT, S = P::S;
+  if constexpr (S > 1) __syncthreads();   // LDS may still be read by a previous use
+  static_for<0, S>([&](auto sI) {
+    constexpr int s = decltype(sI)::value;
+    constexpr int R = P::R[s];
+    constexpr int U = RMAX / R;
+    constexpr int Ns = plan_ns<N, s>();
+    if constexpr (s > 0) {
+      __syncthreads();
+#pragma unroll
+      for (int rho = 0; rho < RMAX; ++rho) {
+        const int o = lidx(j + rho * TT);
+        v[rho] = {lre[o], lim[o]};
+      }
+      if constexpr (s < S - 1) __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = j + u * TT;
+      const int k = b & (Ns - 1);
+      cx<T> a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = v[u + r * U];
+      if constexpr (s > 0) {
+        constexpr int tstep = N / (Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cx<T> w = tw[r * k * tstep];
+          a[r] = (DIR < 0) ? cmul(a[r], w) : cmulc(a[r], w);
+        }
+      }
+      dft<R, DIR, T>(a);
+      if constexpr (s < S - 1) {
+        const int base = (b / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int o = lidx(base + r * Ns);
+          lre[o] = a[r].x;
+          lim[o] = a[r].y;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u + r * U] = a[r];
+      }
+    }
+  });
+}
+
+}  // namespace mag

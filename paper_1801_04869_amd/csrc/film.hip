@@ -1,0 +1,574 @@
+// Thin-film (2D) right-hand side: eq. (9) in the film on a staggered
+// node/edge grid and the free-space iteration (10)-(12) of Prigozhin &
+// Sokolovsky, Sec. 2.
+//
+// Layouts (x fastest): g, dh/dt, G on nodes [ny][nx]; half spectrum [ny][kx],
+// kx = nx/2 + 1.  One inner iteration:
+//   rows_fwd(H)   apply the pending shift A on free-space nodes, R2C of H - dh_e
+//   cols(K1)      y transform, multiply by 2/|k| (and 1/N), inverse y transform
+//   rows_inv(G)   C2R -> G, per-block sums of G over free space
+//   finalize      C = free-space mean of G                           (eq. (11))
+//   rows_fwd(G)   gdot = G - C, per-block sums of |gdot| over free space,
+//                 R2C of gdot masked to free space
+//   finalize      stop test of Sec. 2.3 (sets `done`)
+//   cols(K2)      |k|/2 multiplier
+//   rows_inv(upd) C2R -> V, H -= lambda V on free space, sums of H - dh_e over D
+//   finalize      A = sum / #free-space nodes                        (eq. (10), (12))
+// On convergence gdot = G - C is written to the output in double precision.
+#include <cmath>
+
+#include "ctx.h"
+#include "kern_common.h"
+
+namespace mag {
+
+namespace {
+
+__device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
+
+struct FilmGeom {
+  int nx, ny, kx;
+  double idx, idy;
+};
+
+template <typename T>
+__device__ __forceinline__ T film_rho(T s, T jc, T e0, T nm1, T lmax) {
+  if (!(s > (T)0)) return (T)0;
+  T lg = log(s / jc);
+  if constexpr (sizeof(T) == 4) lg = fminf(lg, lmax);
+  return (e0 / jc) * exp(nm1 * lg);
+}
+
+struct FilmLaw {
+  double e0, nm1, rho_out, lmax, jc0;
+  int has_jc;
+};
+
+// e on the x-edge (p, q+1/2) or the y-edge (p+1/2, q) (orient 0 / 1).
+template <typename T>
+__device__ __forceinline__ T film_edge_e(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+                                         const T *__restrict__ jc, const FilmGeom &G, const FilmLaw &law,
+                                         int p, int q, int orient) {
+  const int nx = G.nx, ny = G.ny;
+  auto gv = [&](int pp, int qq) { return g[(long long)wrap(qq, ny) * nx + wrap(pp, nx)]; };
+  auto jxv = [&](int pp, int qq) { return (gv(pp, qq + 1) - gv(pp, qq)) * G.idy; };
+  auto jyv = [&](int pp, int qq) { return -(gv(pp + 1, qq) - gv(pp, qq)) * G.idx; };
+  double jo, oth;
+  long long c0 = (long long)wrap(q, ny) * nx + wrap(p, nx), c1;
+  if (orient == 0) {
+    jo = jxv(p, q);
+    oth = 0.25 * (jyv(p - 1, q) + jyv(p, q) + jyv(p - 1, q + 1) + jyv(p, q + 1));
+    c1 = (long long)wrap(q, ny) * nx + wrap(p - 1, nx);
+  } else {
+    jo = jyv(p, q);
+    oth = 0.25 * (jxv(p, q - 1) + jxv(p, q) + jxv(p + 1, q - 1) + jxv(p + 1, q));
+    c1 = (long long)wrap(q - 1, ny) * nx + wrap(p, nx);
+  }
+  const uint8_t m0 = mat[c0], m1 = mat[c1];
+  if (m0 == 1 && m1 == 1) {
+    const T jt = (T)jo, ot = (T)oth;
+    const T s = sqrt(jt * jt + ot * ot);
+    const T jce = law.has_jc ? (T)0.5 * (jc[c0] + jc[c1]) : (T)law.jc0;
+    return film_rho(s, jce, (T)law.e0, (T)law.nm1, (T)law.lmax) * jt;
+  }
+  return (T)law.rho_out * (T)jo;
+}
+
+// dh_z/dt = -(d_x e_y - d_y e_x) at inside nodes (eq. (9)); free-space nodes
+// keep the warm start (or take dh_e/dt).  Per-block sums of H - dh_e over D.
+template <typename T>
+__global__ void __launch_bounds__(256) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+                                                    const uint8_t *__restrict__ flags, const T *__restrict__ jc,
+                                                    T *__restrict__ H, FilmGeom G, FilmLaw law, double hde,
+                                                    int warm, double *__restrict__ part) {
+  __shared__ double red[256];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = (long long)G.nx * G.ny;
+  double acc = 0.0;
+  if (i < n) {
+    const int p = (int)(i % G.nx), q = (int)(i / G.nx);
+    T h;
+    if (flags[i] & 1) {
+      const T exq = film_edge_e<T>(g, mat, jc, G, law, p, q, 0);
+      const T exm = film_edge_e<T>(g, mat, jc, G, law, p, q - 1, 0);
+      const T eyp = film_edge_e<T>(g, mat, jc, G, law, p, q, 1);
+      const T eym = film_edge_e<T>(g, mat, jc, G, law, p - 1, q, 1);
+      const double curl = ((double)eyp - (double)eym) * G.idx - ((double)exq - (double)exm) * G.idy;
+      h = (T)(-curl);
+      H[i] = h;
+    } else if (warm) {
+      h = H[i];
+    } else {
+      h = (T)hde;
+      H[i] = h;
+    }
+    acc = (double)h - hde;
+  }
+  const double s = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Row transforms.  MODE 0: H rows (apply shift A on free space, write back,
+// transform H - dh_e).  MODE 1: G rows (gdot = G - C, sums of |gdot| on free
+// space, transform gdot on free space).  MODE 2: rows of a double array.
+template <typename T, int M, int MODE>
+__global__ void __launch_bounds__((RowShape<M, T>::THREADS))
+    film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
+                  cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
+                  FilmGeom G, double hde, double *__restrict__ part, const IterState *__restrict__ it) {
+  if (it->done) return;
+  using RS = RowShape<M, T>;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH;
+  __shared__ T lre[P * PITCH], lim[P * PITCH];
+  __shared__ double red[RS::THREADS];
+  const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  const int q = blockIdx.x * P + pr;
+  const bool active = q < G.ny;
+  const long long ro = (long long)(active ? q : 0) * G.nx;
+  const double shift = MODE == 0 ? it->A : (MODE == 1 ? it->C : 0.0);
+  double acc = 0.0;
+  cx<T> v[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    T val[2] = {(T)0, (T)0};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = 2 * (j + rho * TT) + e;
+      if (!active) continue;
+      if constexpr (MODE == 0) {
+        T h = X[ro + p];
+        if (!(flags[ro + p] & 1)) {
+          h = (T)((double)h - shift);
+          X[ro + p] = h;
+        }
+        val[e] = (T)((double)h - hde);
+      } else if constexpr (MODE == 1) {
+        const double gd = (double)X[ro + p] - shift;
+        if (!(flags[ro + p] & 1)) {
+          acc += fabs(gd);
+          val[e] = (T)gd;
+        }
+      } else {
+        val[e] = (T)xd[ro + p];
+      }
+    }
+    v[rho] = {val[0], val[1]};
+  }
+  T *mre = lre + pr * PITCH, *mim = lim + pr * PITCH;
+  pencil_fft<M, -1>(v, j, mre, mim, [](int i) { return i + (i >> 4); }, twM);
+  r2c_finish<M>(v, j, mre, mim, twN, S + (long long)(active ? q : 0) * G.kx, active);
+  if constexpr (MODE == 1) {
+    const double s = block_sum<RS::THREADS>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+// MODE 0: write G, sums of G over free space.  MODE 1: V -> H -= lambda V on
+// free space, sums of H - dh_e over D.  MODE 2: write hz = h_e + value (double).
+template <typename T, int M, int MODE>
+__global__ void __launch_bounds__((RowShape<M, T>::THREADS))
+    film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
+                  const cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
+                  FilmGeom G, double hde, double lam, double *__restrict__ part,
+                  const IterState *__restrict__ it) {
+  if (it->done) return;
+  using RS = RowShape<M, T>;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH;
+  __shared__ T lre[P * PITCH], lim[P * PITCH];
+  __shared__ double red[RS::THREADS];
+  const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  const int q = blockIdx.x * P + pr;
+  const bool active = q < G.ny;
+  const long long ro = (long long)(active ? q : 0) * G.nx;
+  cx<T> v[RMAX];
+  c2r_start<M>(v, j, S + (long long)(active ? q : 0) * G.kx, twN, active);
+  T *mre = lre + pr * PITCH, *mim = lim + pr * PITCH;
+  pencil_fft<M, +1>(v, j, mre, mim, [](int i) { return i + (i >> 4); }, twM);
+  double acc = 0.0;
+  if (active) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const int m = j + rho * TT;
+      const T val[2] = {v[rho].x, v[rho].y};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int p = 2 * m + e;
+        const bool out = !(flags[ro + p] & 1);
+        if constexpr (MODE == 0) {
+          X[ro + p] = val[e];
+          if (out) acc += (double)val[e];
+        } else if constexpr (MODE == 1) {
+          T h = X[ro + p];
+          if (out) {
+            h = (T)((double)h - lam * (double)val[e]);
+            X[ro + p] = h;
+          }
+          acc += (double)h - hde;
+        } else {
+          xd[ro + p] = hde + (double)val[e];
+        }
+      }
+    }
+  }
+  if constexpr (MODE != 2) {
+    const double s = block_sum<RS::THREADS>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+// Column pass: forward y transform, multiplier K(|k|) / N, inverse y transform.
+// which = 0: 2/|k| (eq. (7), 0 at k = 0); which = 1: |k|/2 (eq. (12)).
+template <typename T, int NY>
+__global__ void __launch_bounds__((ColShape<NY, T>::THREADS))
+    film_cols(cx<T> *__restrict__ S, int kx, const double *__restrict__ k2x, const double *__restrict__ k2y,
+              double inv_n, int which, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
+  if (it->done) return;
+  using CS = ColShape<NY, T>;
+  constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NY>::RMAX;
+  extern __shared__ unsigned char smem_raw[];
+  T *lre = reinterpret_cast<T *>(smem_raw), *lim = lre + NY * P;
+  const int pcol = threadIdx.x % P, j = threadIdx.x / P;
+  const int col = blockIdx.x * P + pcol;
+  const bool active = col < kx;
+  cx<T> *base = S + (active ? col : 0);
+  auto lidx = [pcol](int i) { return i * P + pcol; };
+  cx<T> v[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho)
+    v[rho] = active ? base[(long long)(j + rho * TT) * kx] : cx<T>{(T)0, (T)0};
+  pencil_fft<NY, -1>(v, j, lre, lim, lidx, tw);
+  const double kxx = k2x[active ? col : 0];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const double kk = sqrt(kxx + k2y[j + rho * TT]);
+    double mult;
+    if (which == 0) mult = kk > 0.0 ? 2.0 * inv_n / kk : 0.0;
+    else mult = 0.5 * kk * inv_n;
+    v[rho] = scale(v[rho], (T)mult);
+  }
+  pencil_fft<NY, +1>(v, j, lre, lim, lidx, tw);
+  if (active) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) base[(long long)(j + rho * TT) * kx] = v[rho];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) film_out(const T *__restrict__ Gm, double *__restrict__ out, long long n,
+                                                const IterState *__restrict__ it) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = (double)Gm[i] - it->C;
+}
+
+__global__ void __launch_bounds__(256) film_current(const double *__restrict__ g, double *__restrict__ j, int nx,
+                                                    int ny, double idx, double idy) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = (long long)nx * ny;
+  if (i >= n) return;
+  const int p = (int)(i % nx), q = (int)(i / nx);
+  const double g0 = g[i];
+  j[i] = (g[(long long)wrap(q + 1, ny) * nx + p] - g0) * idy;
+  j[i + n] = -(g[(long long)q * nx + wrap(p + 1, nx)] - g0) * idx;
+}
+
+__global__ void __launch_bounds__(256) sum_blocks(const double *__restrict__ x, long long n,
+                                                  double *__restrict__ part) {
+  __shared__ double red[256];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const double s = block_sum<256>(i < n ? x[i] : 0.0, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+}  // namespace
+
+// ================================================================= host side
+static FilmGeom fgeom(mag_ctx *c) {
+  FilmGeom G;
+  G.nx = c->n[0];
+  G.ny = c->n[1];
+  G.kx = c->kx;
+  G.idx = 1.0 / c->d[0];
+  G.idy = 1.0 / c->d[1];
+  return G;
+}
+
+#define FILM_SWITCH_M(M_, ...)                            \
+  switch (M_) {                                            \
+    case 8: { constexpr int MM = 8; __VA_ARGS__; } break;         \
+    case 16: { constexpr int MM = 16; __VA_ARGS__; } break;       \
+    case 32: { constexpr int MM = 32; __VA_ARGS__; } break;       \
+    case 64: { constexpr int MM = 64; __VA_ARGS__; } break;       \
+    case 128: { constexpr int MM = 128; __VA_ARGS__; } break;     \
+    case 256: { constexpr int MM = 256; __VA_ARGS__; } break;     \
+    case 512: { constexpr int MM = 512; __VA_ARGS__; } break;     \
+    case 1024: { constexpr int MM = 1024; __VA_ARGS__; } break;   \
+    default: return set_error(c, MAG_E_ARG, "unsupported length %d", M_); \
+  }
+
+#define FILM_SWITCH_N(N_, ...)                            \
+  switch (N_) {                                            \
+    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;       \
+    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;       \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;       \
+    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;     \
+    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;     \
+    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;     \
+    case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;   \
+    case 2048: { constexpr int NN = 2048; __VA_ARGS__; } break;   \
+    default: return set_error(c, MAG_E_ARG, "unsupported length %d", N_); \
+  }
+
+template <typename T>
+struct FilmPtrs {
+  T *H, *G;
+  cx<T> *S;
+  const cx<T> *twM, *twY, *twN;
+  const double *k2x, *k2y;
+};
+
+template <typename T>
+static FilmPtrs<T> fptrs(mag_ctx *c) {
+  FilmPtrs<T> f;
+  f.H = reinterpret_cast<T *>(c->d_H);
+  f.G = reinterpret_cast<T *>(c->d_G);
+  f.S = reinterpret_cast<cx<T> *>(c->d_S);
+  const cx<T> *tw = reinterpret_cast<const cx<T> *>(c->d_tw);
+  f.twM = tw + c->tw_off[0];
+  f.twY = tw + c->tw_off[1];
+  f.twN = tw + c->tw_off[3];
+  f.k2x = c->d_sym + c->sym_off[0];
+  f.k2y = c->d_sym + c->sym_off[1];
+  return f;
+}
+
+template <typename T, int MODE>
+static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, int kid) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  ProfScope ps(c, kid);
+  FILM_SWITCH_M(G.nx / 2, {
+    using RS = RowShape<MM, T>;
+    const int nblk = (G.ny + RS::P - 1) / RS::P;
+    hipLaunchKernelGGL((film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
+                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->d_part, c->d_it);
+  });
+  return MAG_OK;
+}
+
+template <typename T, int MODE>
+static int film_inv(mag_ctx *c, T *X, double *xd, double hde, int *nblk_out, int kid) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  ProfScope ps(c, kid);
+  FILM_SWITCH_M(G.nx / 2, {
+    using RS = RowShape<MM, T>;
+    const int nblk = (G.ny + RS::P - 1) / RS::P;
+    *nblk_out = nblk;
+    hipLaunchKernelGGL((film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
+                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, c->d_part, c->d_it);
+  });
+  return MAG_OK;
+}
+
+template <typename T>
+static int film_col(mag_ctx *c, int which) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  ProfScope ps(c, K_FILM_COLS);
+  FILM_SWITCH_N(G.ny, {
+    using CS = ColShape<NN, T>;
+    const int nblk = (G.kx + CS::P - 1) / CS::P;
+    const size_t lds = (size_t)2 * NN * CS::P * sizeof(T);
+    hipLaunchKernelGGL((film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), lds, c->stream, f.S, G.kx, f.k2x, f.k2y,
+                       1.0 / (double)c->nnode, which, f.twY, c->d_it);
+  });
+  return MAG_OK;
+}
+
+template <typename T>
+static int film_iteration(mag_ctx *c, double hde) {
+  const FilmPtrs<T> f = fptrs<T>(c);
+  int rc, nblk = 0;
+  if ((rc = film_fwd<T, 0>(c, f.H, nullptr, hde, K_FILM_ROWS_FWD_H))) return rc;
+  if ((rc = film_col<T>(c, 0))) return rc;
+  if ((rc = film_inv<T, 0>(c, f.G, nullptr, hde, &nblk, K_FILM_ROWS_INV_G))) return rc;
+  if ((rc = run_finalize_mean(c, nblk, 0))) return rc;                 // C
+  if ((rc = film_fwd<T, 1>(c, f.G, nullptr, hde, K_FILM_ROWS_FWD_G))) return rc;
+  if ((rc = run_finalize_stop(c, nblk))) return rc;                    // r, done
+  if ((rc = film_col<T>(c, 1))) return rc;
+  if ((rc = film_inv<T, 1>(c, f.H, nullptr, hde, &nblk, K_FILM_ROWS_INV_UPD))) return rc;
+  return run_finalize_mean(c, nblk, 1);                                // A
+}
+
+template <typename T>
+static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, int *n_inner) {
+  double hd[3];
+  field_hdot(c, t, hd);
+  const double hde = hd[2];
+  const FilmGeom G = fgeom(c);
+  FilmPtrs<T> f = fptrs<T>(c);
+  IterState is{};
+  is.fixed = c->fixed_iters;
+  is.thr = c->tol * (std::fabs(hde) > 1.0 ? std::fabs(hde) : 1.0);
+  is.inv_nout = c->nout > 0 ? 1.0 / (double)c->nout : 0.0;
+  *c->h_it = is;
+  MAG_HIP(c, hipMemcpyAsync(c->d_it, c->h_it, sizeof(IterState), hipMemcpyHostToDevice, c->stream));
+  FilmLaw law;
+  law.e0 = c->e0;
+  law.nm1 = c->nexp - 1.0;
+  law.rho_out = c->rho_out;
+  law.lmax = std::log(1e30) / (c->nexp - 1.0 > 1e-12 ? c->nexp - 1.0 : 1e-12);
+  law.jc0 = c->jc0;
+  law.has_jc = c->has_jc_map ? 1 : 0;
+  const long long n = c->nnode;
+  const int nb = (int)((n + 255) / 256);
+  {
+    ProfScope ps(c, K_FILM_STENCIL);
+    hipLaunchKernelGGL((film_stencil<T>), dim3(nb), dim3(256), 0, c->stream, state, c->d_mat, c->d_flags,
+                       reinterpret_cast<const T *>(c->d_jc), f.H, G, law, hde, c->warm_valid ? 1 : 0, c->d_part);
+  }
+  int rc = run_finalize_mean(c, nb, 1);   // A^0
+  if (rc) return rc;
+  MAG_HIP(c, hipGetLastError());
+  const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
+  int issued = 0;
+  int block = c->fixed_iters > 0 ? c->fixed_iters : (c->last_iters > 0 ? c->last_iters : 1);
+  bool done = false;
+  while (issued < kmax) {
+    const int k = block < kmax - issued ? block : kmax - issued;
+    for (int i = 0; i < k; ++i) {
+      c->cur_iter = issued + i;
+      if ((rc = film_iteration<T>(c, hde))) return rc;
+    }
+    c->cur_iter = -1;
+    issued += k;
+    MAG_HIP(c, hipGetLastError());
+    MAG_HIP(c, hipMemcpyAsync(c->h_it, c->d_it, sizeof(IterState), hipMemcpyDeviceToHost, c->stream));
+    MAG_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->h_it->done) {
+      done = true;
+      break;
+    }
+    block = 1;
+  }
+  const int used = c->h_it->iters;
+  prof_drop_after(c, used);
+  if (n_inner) *n_inner = used;
+  if (!done) {
+    c->warm_valid = false;
+    return set_error(c, MAG_NOT_CONVERGED, "inner iteration not converged after %d iterations (r = %g)", used,
+                     c->h_it->r);
+  }
+  if (!std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C)) {
+    c->warm_valid = false;
+    return set_error(c, MAG_E_NUMERIC, "non-finite residual");
+  }
+  c->last_iters = used;
+  c->warm_valid = true;
+  {
+    ProfScope ps(c, K_MISC);
+    hipLaunchKernelGGL((film_out<T>), dim3(nb), dim3(256), 0, c->stream, f.G, out, n, c->d_it);
+  }
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
+int film_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner) {
+  return c->prec == MAG_FP64 ? film_rhs_t<double>(c, state, t, out, n_inner)
+                             : film_rhs_t<float>(c, state, t, out, n_inner);
+}
+
+template <typename T>
+static int film_observe_t(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m) {
+  const FilmGeom G = fgeom(c);
+  const long long n = c->nnode;
+  const int nb = (int)((n + 255) / 256);
+  double he[3];
+  field_h(c, t, he);
+  IterState is{};
+  *c->h_it = is;
+  MAG_HIP(c, hipMemcpyAsync(c->d_it, c->h_it, sizeof(IterState), hipMemcpyHostToDevice, c->stream));
+  int rc, nblk = 0;
+  if (hz) {
+    if ((rc = film_fwd<T, 2>(c, nullptr, state, 0.0, K_MISC))) return rc;
+    if ((rc = film_col<T>(c, 1))) return rc;
+    if ((rc = film_inv<T, 2>(c, nullptr, hz, he[2], &nblk, K_MISC))) return rc;
+  }
+  if (j) hipLaunchKernelGGL(film_current, dim3(nb), dim3(256), 0, c->stream, state, j, G.nx, G.ny, G.idx, G.idy);
+  // m_z = sum g dx dy: fixed-order two-level sum
+  hipLaunchKernelGGL(sum_blocks, dim3(nb), dim3(256), 0, c->stream, state, n, c->d_part);
+  std::vector<double> parts(nb);
+  MAG_HIP(c, hipGetLastError());
+  MAG_HIP(c, hipMemcpyAsync(parts.data(), c->d_part, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += parts[i];
+  m[0] = 0.0;
+  m[1] = 0.0;
+  m[2] = s * c->d[0] * c->d[1];
+  return MAG_OK;
+}
+
+int film_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m) {
+  return c->prec == MAG_FP64 ? film_observe_t<double>(c, state, t, hz, j, m)
+                             : film_observe_t<float>(c, state, t, hz, j, m);
+}
+
+// ------------------------------------------------------------------ setup
+int film_alloc(mag_ctx *c) {
+  const size_t ts = c->prec == MAG_FP64 ? 8 : 4;
+  const long long n = c->nnode;
+  MAG_HIP(c, hipMalloc(&c->d_H, n * ts));
+  MAG_HIP(c, hipMalloc(&c->d_G, n * ts));
+  MAG_HIP(c, hipMalloc(&c->d_S, c->nspec * 2 * ts));
+  MAG_HIP(c, hipMalloc(&c->d_flags, n));
+  MAG_HIP(c, hipMalloc(&c->d_mat, n));
+  c->npart = (int)((n + 255) / 256 + 16);
+  MAG_HIP(c, hipMalloc(&c->d_part, (size_t)c->npart * sizeof(double)));
+  MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
+  MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
+  // |k|^2 per axis: k = 2 pi fftfreq(n, d)
+  const int nx = c->n[0], ny = c->n[1];
+  std::vector<double> sym;
+  c->sym_off[0] = 0;
+  for (int m = 0; m < c->kx; ++m) {
+    const double k = 2.0 * M_PI * (double)(m <= nx / 2 ? m : m - nx) / (nx * c->d[0]);
+    sym.push_back(k * k);
+  }
+  c->sym_off[1] = (long long)sym.size();
+  for (int m = 0; m < ny; ++m) {
+    const double k = 2.0 * M_PI * (double)(m < (ny + 1) / 2 ? m : m - ny) / (ny * c->d[1]);
+    sym.push_back(k * k);
+  }
+  MAG_HIP(c, hipMalloc(&c->d_sym, sym.size() * sizeof(double)));
+  MAG_HIP(c, hipMemcpy(c->d_sym, sym.data(), sym.size() * sizeof(double), hipMemcpyHostToDevice));
+  return MAG_OK;
+}
+
+int film_domain(mag_ctx *c) {
+  const int nx = c->n[0], ny = c->n[1];
+  const long long n = c->nnode;
+  const std::vector<uint8_t> &m = c->h_mat;
+  std::vector<uint8_t> fl(n, 0);
+  auto F = [&](int p, int q) { return m[(long long)(q & (ny - 1)) * nx + (p & (nx - 1))] != 0; };
+  long long nin = 0;
+  for (int q = 0; q < ny; ++q)
+    for (int p = 0; p < nx; ++p) {
+      const bool in = F(p, q) && F(p - 1, q) && F(p, q - 1) && F(p - 1, q - 1);
+      fl[(long long)q * nx + p] = in ? 1 : 0;
+      nin += in;
+    }
+  if (nin == 0) return set_error(c, MAG_E_ARG, "material has no inside node: empty film");
+  if (nin == n) return set_error(c, MAG_E_ARG, "material leaves no free-space node");
+  c->nout = n - nin;
+  for (int a = 0; a < 2; ++a) {
+    c->box0[a] = 0;
+    c->box1[a] = c->n[a] - 1;
+  }
+  MAG_HIP(c, hipMemcpy(c->d_flags, fl.data(), n, hipMemcpyHostToDevice));
+  MAG_HIP(c, hipMemcpy(c->d_mat, m.data(), n, hipMemcpyHostToDevice));
+  c->warm_valid = false;
+  return MAG_OK;
+}
+
+}  // namespace mag

@@ -1,0 +1,78 @@
+"""Shared problem builders for the GPU parity tests: the same seeded inputs
+(from the workloads module) feed the HIP library and the oracle."""
+import numpy as np
+
+from paper_1801_04869_amd import workloads as W
+
+
+def film_case(nx, ny, L=(2.0, 2.0), kind="rect", n=19.0, jc_s=0.0, seed=1801, rho_out=1.0, field=None):
+    Lx, Ly = L
+    if kind == "rect":
+        mat = W.film_rect(nx, ny, Lx, Ly, 0.5 * Lx, 0.5 * Ly)
+    elif kind == "offrect":
+        mat = W.film_rect(nx, ny, Lx, Ly, 0.37 * Lx, 0.61 * Ly)
+        mat = np.roll(mat, (ny // 9, nx // 7), axis=(0, 1))
+    elif kind == "ring":
+        mat = W.film_ring(nx, ny, Lx, Ly, 0.25 * Lx, 0.5 * Lx)
+    elif kind == "slot":
+        mat = W.film_slot(nx, ny, Lx, Ly, 0.5 * Lx, 8)
+    elif kind == "disk":
+        mat = W.film_disk(nx, ny, Lx, Ly, 0.5 * Lx)
+    else:
+        raise KeyError(kind)
+    jc = W.lognormal_jc((ny, nx), jc_s, 4.0, seed) if jc_s > 0 else None
+    g = W.film_snapshot(mat, 2 * Lx / nx, delta=0.2 * Lx, seed=seed)
+    field = field or dict(kind=0, dir=(0, 0, 1), amp=1.0, omega=1.0, rate=1.0)
+    return dict(dim=2, n=(nx, ny, 1), L=(Lx, Ly, 1.0), mat=mat, jc=jc, state=g, nexp=n, rho_out=rho_out,
+                field=field)
+
+
+def bulk_case(nx, ny, nz, L=(2.0, 2.0, 2.0), half=(1.0, 1.0, 1.0), n=25.0, jc_s=0.0, seed=1803, rho_out=1.0,
+              field=None, shift=(0, 0, 0), t_snap=0.2):
+    Lx, Ly, Lz = L
+    mat = W.bulk_box(nx, ny, nz, Lx, Ly, Lz, *half)
+    mat = np.roll(mat, shift, axis=(0, 1, 2))
+    jc = W.lognormal_jc((nz, ny, nx), jc_s, 3.0, seed) if jc_s > 0 else None
+    field = field or dict(kind=0, dir=(0.5, 0.0, np.sqrt(0.75)), amp=1.0, omega=1.0, rate=1.0)
+    from oracle.field import AppliedField
+    he = AppliedField(field["kind"], field["dir"], field["amp"], field["omega"], field["rate"]).h(t_snap)
+    h = W.bulk_snapshot(mat, 2 * Lx / nx, he, delta=0.3 * min(half), seed=seed + 1)
+    return dict(dim=3, n=(nx, ny, nz), L=(Lx, Ly, Lz), mat=mat, jc=jc, state=h, nexp=n, rho_out=rho_out,
+                field=field)
+
+
+def make_gpu(case, precision=0, lam=0.7, tol=None, max_inner=100, fixed=0):
+    import torch
+    from paper_1801_04869_amd import api
+    c = api.Context(case["dim"], precision)
+    nx, ny, nz = case["n"]
+    c.set_grid(nx, ny, nz, *case["L"])
+    c.set_domain(torch.from_numpy(np.ascontiguousarray(case["mat"])).cuda())
+    jc = None if case["jc"] is None else torch.from_numpy(np.ascontiguousarray(case["jc"])).cuda()
+    c.set_params(jc, 1.0, case["nexp"], 1.0, case["rho_out"])
+    c.set_solver(lam, tol, max_inner, fixed)
+    f = case["field"]
+    c.set_field(f["kind"], f["dir"], f["amp"], f["omega"], f["rate"])
+    return c
+
+
+def make_oracle(case, lam=0.7, tol=None, max_inner=100, fixed=0):
+    from oracle import bulk, film
+    from oracle.field import AppliedField
+    f = case["field"]
+    fld = AppliedField(f["kind"], f["dir"], f["amp"], f["omega"], f["rate"])
+    nx, ny, nz = case["n"]
+    if case["dim"] == 2:
+        return film.FilmProblem(nx, ny, case["L"][0], case["L"][1], case["mat"], jc_cell=case["jc"],
+                                n=case["nexp"], rho_out=case["rho_out"], lam=lam,
+                                tol=2e-4 if tol is None else tol, max_inner=max_inner, fixed_iters=fixed,
+                                field=fld)
+    return bulk.BulkProblem(nx, ny, nz, *case["L"], case["mat"], jc_cell=case["jc"], n=case["nexp"],
+                            rho_out=case["rho_out"], tol=1e-4 if tol is None else tol, max_inner=max_inner,
+                            fixed_iters=fixed, field=fld)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))

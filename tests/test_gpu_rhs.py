@@ -1,0 +1,276 @@
+"""GPU parity of the right-hand side, the observables and the time stepping
+against the FP64 oracle, through the C ABI (HIP library only).
+
+Tolerances (relative L2, as fixed for this method): 1e-10 for the FP64 form,
+1e-4 for the mixed form (float FFTs, multipliers and power law; double state,
+sums and step control).
+"""
+import numpy as np
+import pytest
+
+from tests._cases import bulk_case, film_case, make_gpu, make_oracle, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import bulk, film  # noqa: E402
+from paper_1801_04869_amd import api  # noqa: E402
+
+TOL = {api.FP64: 1e-10, api.MIXED: 1e-4}
+
+
+def _gpu_rhs(ctx, state, t):
+    s = torch.from_numpy(np.ascontiguousarray(state)).cuda()
+    out = torch.empty_like(s)
+    st, it = ctx.rhs(s, t, out)
+    torch.cuda.synchronize()
+    return st, it, out.cpu().numpy()
+
+
+def _ora_rhs(prob, case, t):
+    mod = film if case["dim"] == 2 else bulk
+    return mod.rhs(prob, case["state"], t)
+
+
+# ------------------------------------------------------------------ bulk
+BULK_CASES = [
+    dict(n=(32, 32, 32)),
+    dict(n=(64, 32, 16), L=(4.0, 2.0, 1.0), half=(1.3, 0.7, 0.45), shift=(1, -2, 3)),
+    dict(n=(16, 64, 32), L=(1.0, 4.0, 2.0), half=(0.45, 1.1, 0.7), jc_s=0.2, n_exp=50.0),
+]
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("ci", range(len(BULK_CASES)))
+@pytest.mark.parametrize("fixed", [1, 3])
+def test_bulk_rhs_fixed_iterations(prec, ci, fixed):
+    kw = dict(BULK_CASES[ci])
+    nexp = kw.pop("n_exp", 25.0)
+    case = bulk_case(*kw.pop("n"), n=nexp, **kw)
+    print("bulk fixed", case["n"], prec, fixed, flush=True)
+    ctx = make_gpu(case, prec, fixed=fixed)
+    prob = make_oracle(case, fixed=fixed)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.2)
+    ref, rit, rst = _ora_rhs(prob, case, 0.2)
+    assert st == 0 and rst == 0 and it == rit == fixed
+    assert rel_l2(out, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+def test_bulk_rhs_converged_and_warm_start_sequence(prec):
+    case = bulk_case(32, 32, 32, n=25.0, jc_s=0.15)
+    ctx = make_gpu(case, prec)
+    prob = make_oracle(case)
+    rng = np.random.default_rng(5)
+    for k, t in enumerate([0.2, 0.21, 0.23]):
+        state = case["state"] + (1e-3 * k) * rng.standard_normal(case["state"].shape) * 0.01
+        st, it, out = _gpu_rhs(ctx, state, t)
+        ref, rit, rst = bulk.rhs(prob, state, t)
+        print("call", k, it, rit, flush=True)
+        assert st == 0 and rst == 0
+        if prec == api.FP64:
+            assert it == rit
+            assert rel_l2(out, ref) < TOL[prec]
+        else:
+            assert abs(it - rit) <= 1
+            assert rel_l2(out, ref) < 10 * prob.tol
+
+
+def test_bulk_converged_stray_current_vanishes():
+    case = bulk_case(64, 64, 64, n=25.0)
+    ctx = make_gpu(case, api.FP64, tol=1e-10, max_inner=200)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.2)
+    assert st == 0
+    prob = make_oracle(case)
+    j = bulk.curl(prob, out)
+    assert np.abs(j[~prob.in_face]).max() < 1e-7 * np.abs(j).max()
+
+
+def test_bulk_observables():
+    case = bulk_case(32, 64, 32, L=(2.0, 4.0, 2.0), jc_s=0.1)
+    ctx = make_gpu(case)
+    prob = make_oracle(case)
+    s = torch.from_numpy(case["state"]).cuda()
+    hz, j, m = ctx.observe(s, 0.3)
+    rhz, rj, rm = bulk.observe(prob, case["state"], 0.3)
+    assert rel_l2(hz.cpu().numpy(), rhz) < 1e-14
+    assert rel_l2(j.cpu().numpy(), rj) < 1e-12
+    assert np.allclose(m, rm, rtol=1e-10, atol=1e-12 * np.abs(rm).max())
+
+
+# ------------------------------------------------------------------ film
+FILM_CASES = [
+    dict(nx=64, ny=64, kind="rect"),
+    dict(nx=128, ny=32, L=(4.0, 1.0), kind="offrect", jc_s=0.2),
+    dict(nx=64, ny=128, L=(2.0, 4.0), kind="ring", rho_out=50.0),
+    dict(nx=128, ny=128, kind="slot", n=30.0),
+]
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("ci", range(len(FILM_CASES)))
+@pytest.mark.parametrize("fixed", [1, 4])
+def test_film_rhs_fixed_iterations(prec, ci, fixed):
+    case = film_case(**FILM_CASES[ci])
+    print("film fixed", case["n"], prec, fixed, flush=True)
+    ctx = make_gpu(case, prec, fixed=fixed)
+    prob = make_oracle(case, fixed=fixed)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.1)
+    ref, rit, rst = _ora_rhs(prob, case, 0.1)
+    assert st == 0 and rst == 0 and it == rit == fixed
+    assert rel_l2(out, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+def test_film_rhs_converged_sequence(prec):
+    case = film_case(128, 128, kind="rect", jc_s=0.2)
+    ctx = make_gpu(case, prec)
+    prob = make_oracle(case)
+    for k, t in enumerate([0.1, 0.11, 0.13, 0.2]):
+        st, it, out = _gpu_rhs(ctx, case["state"] * (1 + 0.01 * k), t)
+        ref, rit, rst = film.rhs(prob, case["state"] * (1 + 0.01 * k), t)
+        print("call", k, it, rit, flush=True)
+        assert st == 0 and rst == 0
+        if prec == api.FP64:
+            assert it == rit
+            assert rel_l2(out, ref) < TOL[prec]
+        else:
+            assert abs(it - rit) <= 1
+
+
+def test_film_observables():
+    case = film_case(64, 128, L=(2.0, 4.0), kind="ring", jc_s=0.1)
+    ctx = make_gpu(case)
+    prob = make_oracle(case)
+    s = torch.from_numpy(case["state"]).cuda()
+    hz, j, m = ctx.observe(s, 0.3)
+    rhz, (rjx, rjy), rm = film.observe(prob, case["state"], 0.3)
+    assert rel_l2(hz.cpu().numpy(), rhz) < 1e-12
+    assert rel_l2(j.cpu().numpy(), np.stack([rjx, rjy])) < 1e-13
+    assert abs(m[2] - rm) < 1e-12 * abs(rm)
+
+
+# ------------------------------------------------------------------ time stepping
+def _replay_steps(ctx, prob, case, mod, steps, t0):
+    """Take the given step sizes on both sides with the same call order."""
+    y = torch.from_numpy(np.ascontiguousarray(case["state"])).cuda()
+    t = t0
+    k1, st = mod.rhs(prob, case["state"], t0)
+    yo = case["state"].copy()
+    for h in steps:
+        t_new, dt_next, acc = ctx.step(y, t, h, rtol=1e-3, atol=1e-6)
+        f = lambda tt, yy: mod.rhs(prob, yy, tt)[::2]
+        ynew, k4, err, st = __import__("oracle.bs23", fromlist=["attempt"]).attempt(f, t, yo, h, k1)
+        from oracle import bs23
+        en = bs23.error_norm(err, yo, ynew, 1e-3, 1e-6)
+        assert acc == (en <= 1.0)
+        if acc:
+            yo, k1, t = ynew, k4, t + h
+        assert t_new == t
+    return y.cpu().numpy(), yo
+
+
+def test_film_steps_match_oracle():
+    case = film_case(64, 64, kind="rect", n=19.0)
+    ctx = make_gpu(case, api.FP64)
+    prob = make_oracle(case)
+    ygpu, yora = _replay_steps(ctx, prob, case, film, [2e-3, 5e-3, 1e-2, 4e-3], 0.1)
+    assert rel_l2(ygpu, yora) < 1e-10
+
+
+def test_bulk_steps_match_oracle():
+    case = bulk_case(32, 32, 32, n=25.0)
+    ctx = make_gpu(case, api.FP64)
+    prob = make_oracle(case)
+    ygpu, yora = _replay_steps(ctx, prob, case, bulk, [1e-4, 3e-4, 2e-4], 0.2)
+    assert rel_l2(ygpu, yora) < 1e-10
+
+
+def test_film_integrate_matches_oracle():
+    """Adaptive integration of the 64x64-cell square film (128^2 grid, n = 19,
+    h_e = t up to 0.5): same accepted steps, state, h_z, j and moment."""
+    from oracle import bs23
+    case = film_case(128, 128, kind="rect", n=19.0)
+    case["state"] = np.zeros_like(case["state"])
+    ctx = make_gpu(case, api.FP64)
+    prob = make_oracle(case)
+    y = torch.zeros(128, 128, dtype=torch.float64, device="cuda")
+    nsteps, obs = ctx.integrate(y, 0.0, 0.5, obs_cap=10000)
+
+    def f(t, yy):
+        v, it, st = film.rhs(prob, yy.reshape(128, 128), t)
+        return (None if v is None else v.ravel()), st
+
+    yo, to, hist = bs23.integrate(f, np.zeros(128 * 128), 0.0, 0.5)
+    print("steps gpu", nsteps, "oracle", len(hist), flush=True)
+    assert nsteps == len(hist)
+    assert rel_l2(y.cpu().numpy().ravel(), yo) < 1e-9
+    hz, j, m = ctx.observe(y, 0.5)
+    rhz, (rjx, rjy), rm = film.observe(prob, yo.reshape(128, 128), 0.5)
+    assert rel_l2(hz.cpu().numpy(), rhz) < 1e-9
+    assert rel_l2(j.cpu().numpy(), np.stack([rjx, rjy])) < 1e-9
+    assert abs(m[2] - rm) < 1e-9 * abs(rm)
+    assert abs(obs[-1][0] - 0.5) < 1e-14
+
+
+# ------------------------------------------------------------------ edge cases
+def test_argument_and_state_errors():
+    c = api.Context(3, api.FP64)
+    with pytest.raises(api.MagError) as e:
+        c.set_grid(48, 32, 32, 1, 1, 1)
+    assert e.value.code == api.E_ARG
+    with pytest.raises(api.MagError) as e:
+        c.set_domain(torch.zeros(8, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == api.E_STATE
+    c.set_grid(16, 16, 16, 1, 1, 1)
+    with pytest.raises(api.MagError) as e:
+        c.set_domain(torch.zeros(16, 16, 16, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == api.E_ARG
+    bad = torch.full((16, 16, 16), 3, dtype=torch.uint8, device="cuda")
+    with pytest.raises(api.MagError) as e:
+        c.set_domain(bad)
+    assert e.value.code == api.E_ARG
+    s = torch.zeros(3, 16, 16, 16, dtype=torch.float64, device="cuda")
+    with pytest.raises(api.MagError) as e:
+        c.rhs(s, 0.0, torch.empty_like(s))
+    assert e.value.code == api.E_STATE
+
+
+def test_nonfinite_state_is_reported_not_hung():
+    case = bulk_case(32, 32, 32)
+    ctx = make_gpu(case)
+    st = case["state"].copy()
+    st[2, 16, 16, 16] = np.nan
+    s = torch.from_numpy(st).cuda()
+    out = torch.empty_like(s)
+    with pytest.raises(api.MagError) as e:
+        ctx.rhs(s, 0.2, out)
+    assert e.value.code == api.E_NUMERIC
+
+
+def test_not_converged_status_and_recovery():
+    case = film_case(64, 64, kind="rect")
+    ctx = make_gpu(case, api.FP64, max_inner=1)
+    s = torch.from_numpy(case["state"]).cuda()
+    out = torch.empty_like(s)
+    st, it = ctx.rhs(s, 0.1, out)
+    assert st == api.NOT_CONVERGED and it == 1
+    ctx.set_solver(0.7, 2e-4, 100, 0)
+    st, it = ctx.rhs(s, 0.1, out)
+    prob = make_oracle(case)
+    ref, rit, _ = film.rhs(prob, case["state"], 0.1)
+    assert st == 0 and it == rit
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-10
+
+
+def test_sample_touching_periodic_boundary():
+    """A sample reaching the box edge disables pruning on that axis."""
+    case = bulk_case(32, 32, 32, half=(1.0, 1.0, 1.0), shift=(16, 0, 0))
+    ctx = make_gpu(case, api.FP64, fixed=2)
+    prob = make_oracle(case, fixed=2)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.2)
+    ref, _, _ = bulk.rhs(prob, case["state"], 0.2)
+    assert rel_l2(out, ref) < 1e-10
