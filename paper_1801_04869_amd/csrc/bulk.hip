@@ -610,8 +610,8 @@ int bulk_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_S, 3 * c->nspec * 2 * ts));
   MAG_HIP(c, hipMalloc(&c->d_flags, N));
   MAG_HIP(c, hipMalloc(&c->d_mat, N));
-  // per-block partials: x_inv blocks x 3 (rows / P with P >= 4)
-  c->npart = (int)(3 * ((long long)c->n[1] * c->n[2] / 4 + 1));
+  // per-block partials: at most one x_inv block per row, times 3 components
+  c->npart = (int)(3LL * c->n[1] * c->n[2] + 16);
   MAG_HIP(c, hipMalloc(&c->d_part, (size_t)c->npart * sizeof(double)));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, 3 * N * ts, c->stream));
   // symbol tables: dm (complex) for x (kx entries), y, z; k2 for x, y, z

@@ -523,7 +523,7 @@ int film_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_S, c->nspec * 2 * ts));
   MAG_HIP(c, hipMalloc(&c->d_flags, n));
   MAG_HIP(c, hipMalloc(&c->d_mat, n));
-  c->npart = (int)((n + 255) / 256 + 16);
+  c->npart = (int)((n + 255) / 256 + c->n[1] + 16);   // stencil blocks or one row block per row
   MAG_HIP(c, hipMalloc(&c->d_part, (size_t)c->npart * sizeof(double)));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
   MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
