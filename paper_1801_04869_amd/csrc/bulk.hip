@@ -32,6 +32,14 @@ struct BulkGeom {
   double idx, idy, idz;               // 1/d
 };
 
+// Box-local index of a stencil neighbour.  When the box spans a whole
+// periodic axis (b0 = 0, b1 = n - 1) its two halo layers are copies of the
+// last and first interior layers; fold them onto the interior.
+__device__ __forceinline__ int fold(int l, int b0, int b1, int n) {
+  if (b0 == 0 && b1 == n - 1) return ((l - 1 + n) % n) + 1;
+  return l;
+}
+
 // ------------------------------------------------------------ stencil pass
 // j = curl h on the faces of the extended box [b0-1, b1+1] (double arithmetic
 // from the double state, stored in T).
@@ -134,7 +142,10 @@ __global__ void __launch_bounds__(256) bulk_hdot_in(const T *__restrict__ eb, T 
   const long long gi = ((long long)r * g.ny + q) * g.nx + p;
   const uint8_t f = flags[gi];
   if (!(f & 0x38)) return;
-  auto L = [&](int a, int b, int c) { return ((long long)c * by + b) * bx + a; };
+  auto L = [&](int a, int b, int c) {
+    return ((long long)fold(c, g.b0z, g.b1z, g.nz) * by + fold(b, g.b0y, g.b1y, g.ny)) * bx +
+           fold(a, g.b0x, g.b1x, g.nx);
+  };
   const T *ex = eb, *ey = eb + nbox, *ez = eb + 2 * nbox;
   const long long o = L(lx, ly, lz);
   if (f & 0x08) {
@@ -228,7 +239,7 @@ __global__ void __launch_bounds__((ColShape<NN, T>::THREADS))
   if (it->done) return;
   using CS = ColShape<NN, T>;
   constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NN>::RMAX;
-  extern __shared__ unsigned char smem_raw[];
+  HIP_DYNAMIC_SHARED(unsigned char, smem_raw)
   T *lre = reinterpret_cast<T *>(smem_raw), *lim = lre + NN * P;
   const int pcol = threadIdx.x % P, j = threadIdx.x / P;
   const int ngrp = (ncols + P - 1) / P;
@@ -264,7 +275,7 @@ __global__ void __launch_bounds__((ColShape<NZ, T>::THREADS))
   if (it->done) return;
   using CS = ColShape<NZ, T>;
   constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NZ>::RMAX;
-  extern __shared__ unsigned char smem_raw[];
+  HIP_DYNAMIC_SHARED(unsigned char, smem_raw)
   T *lre = reinterpret_cast<T *>(smem_raw), *lim = lre + NZ * P;
   const int pcol = threadIdx.x % P, j = threadIdx.x / P;
   const int ngrp = (kx + P - 1) / P;
@@ -756,6 +767,7 @@ int bulk_observe(mag_ctx *c, const double *state, double t, double *hz, double *
   double *part = nullptr;
   MAG_HIP(c, hipMallocAsync((void **)&part, (size_t)nb * 3 * sizeof(double), c->stream));
   if (hz) MAG_HIP(c, hipMemcpyAsync(hz, state + 2 * N, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  ProfScope ps(c, K_MISC);
   hipLaunchKernelGGL(bulk_obs_k, dim3(nb), dim3(256), 0, c->stream, state, j, c->n[0], c->n[1], c->n[2], c->d[0],
                      c->d[1], c->d[2], c->L[0], c->L[1], c->L[2], part);
   MAG_HIP(c, hipGetLastError());

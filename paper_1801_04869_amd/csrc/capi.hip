@@ -76,10 +76,19 @@ static hipEvent_t pool_get(mag_ctx *c) {
   return e;
 }
 
+static const char *kNames[K_COUNT] = {
+    "film_stencil", "film_rows_fwd_h", "film_cols", "film_rows_inv_g", "film_rows_fwd_g", "film_rows_inv_upd",
+    "bulk_curl_box", "bulk_efield_box", "bulk_hdot_in", "bulk_x_fwd", "bulk_y_fwd", "bulk_z_phi",
+    "bulk_y_inv", "bulk_x_inv", "finalize", "misc", "rk", "vjp"};
+
 void prof_begin(mag_ctx *c, int kid, ProfRec *r) {
   r->a = r->b = nullptr;
   r->kid = kid;
   r->iter = c->cur_iter;
+  if (c->debug_sync) {
+    fprintf(stderr, "[magfft] launch %s (iteration %d)\n", kNames[kid], c->cur_iter);
+    fflush(stderr);
+  }
   if (!c->prof_on) return;
   r->a = pool_get(c);
   r->b = pool_get(c);
@@ -87,6 +96,12 @@ void prof_begin(mag_ctx *c, int kid, ProfRec *r) {
 }
 
 void prof_end(mag_ctx *c, ProfRec *r) {
+  if (c->debug_sync) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    fprintf(stderr, "[magfft]   %s -> %s\n", kNames[r->kid], e == hipSuccess ? "ok" : hipGetErrorString(e));
+    fflush(stderr);
+  }
   if (!c->prof_on || !r->a || !r->b) return;
   (void)hipEventRecord(r->b, c->stream);
   c->prof.push_back(*r);
@@ -265,11 +280,6 @@ using namespace mag;
 // ==================================================================== C ABI
 extern "C" {
 
-static const char *kNames[K_COUNT] = {
-    "film_stencil", "film_rows_fwd_h", "film_cols", "film_rows_inv_g", "film_rows_fwd_g", "film_rows_inv_upd",
-    "bulk_curl_box", "bulk_efield_box", "bulk_hdot_in", "bulk_x_fwd", "bulk_y_fwd", "bulk_z_phi",
-    "bulk_y_inv", "bulk_x_inv", "finalize", "misc", "rk", "vjp"};
-
 static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 
 static void free_all(mag_ctx *c) {
@@ -297,6 +307,8 @@ int mag_create(mag_ctx **out, int dim, int precision, void *hip_stream) {
   c->ncomp = dim == 3 ? 3 : 1;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (dim == 3) c->tol = 1e-4;
+  const char *dbg = getenv("MAG_DEBUG_SYNC");
+  c->debug_sync = dbg && dbg[0] == '1';
   if (hipHostMalloc(&c->h_it, sizeof(IterState)) != hipSuccess) {
     delete c;
     return MAG_E_HIP;
@@ -378,12 +390,15 @@ int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, doubl
   MAG_HIP(c, hipMalloc(&c->d_tw, ntw * 2 * ts));
   MAG_HIP(c, hipMalloc(&tmp, tw.size() * sizeof(double)));
   MAG_HIP(c, hipMemcpy(tmp, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+  {
+  ProfScope ps(c, K_MISC);
   if (c->prec == MAG_FP64)
     hipLaunchKernelGGL((fill_twiddles<double>), dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, c->stream,
                        reinterpret_cast<cx<double> *>(c->d_tw), tmp, ntw);
   else
     hipLaunchKernelGGL((fill_twiddles<float>), dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, c->stream,
                        reinterpret_cast<cx<float> *>(c->d_tw), tmp, ntw);
+  }
   MAG_HIP(c, hipGetLastError());
   MAG_HIP(c, hipStreamSynchronize(c->stream));
   MAG_HIP(c, hipFree(tmp));
@@ -429,6 +444,7 @@ int mag_set_params(mag_ctx *c, const double *jc_map, double jc0, double n, doubl
     MAG_HIP(c, hipMalloc(&tmp, c->nnode * sizeof(double)));
     MAG_HIP(c, hipMemcpy(tmp, h.data(), c->nnode * sizeof(double), hipMemcpyHostToDevice));
     const unsigned nb = (unsigned)((c->nnode + 255) / 256);
+    ProfScope ps(c, K_MISC);
     if (c->prec == MAG_FP64)
       hipLaunchKernelGGL((scale_jc<double>), dim3(nb), dim3(256), 0, c->stream, tmp,
                          reinterpret_cast<double *>(c->d_jc), c->d_jc64, jc0, c->nnode);
@@ -623,7 +639,10 @@ int mag_integrate(mag_ctx *c, double *state, double t0, double t1, double rtol, 
   c->fsal_t = t;
   if ((rc = ensure_red(c, n))) return rc;
   const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(rk_ratio_k, dim3(nb), dim3(256), 0, c->stream, rk_buf(c, c->rk_k1), state, atol / rtol, n, c->d_red);
+  {
+    ProfScope ps(c, K_RK);
+    hipLaunchKernelGGL(rk_ratio_k, dim3(nb), dim3(256), 0, c->stream, rk_buf(c, c->rk_k1), state, atol / rtol, n, c->d_red);
+  }
   MAG_HIP(c, hipGetLastError());
   double mx = 0.0;
   if ((rc = host_max(c, nb, &mx))) return rc;
@@ -704,6 +723,6 @@ int mag_prof_read(mag_ctx *c, int id, int *count, double *total_ms) {
   return MAG_OK;
 }
 
-const char *mag_prof_kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kNames[id] : nullptr; }
+const char *mag_prof_kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? mag::kNames[id] : nullptr; }
 
 }  // extern "C"

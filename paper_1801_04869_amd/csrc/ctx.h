@@ -125,6 +125,7 @@ struct mag_ctx {
   long long adj_bytes = 0;
 
   // instrumentation
+  bool debug_sync = false;        // MAG_DEBUG_SYNC=1: synchronise and check after every launch
   bool prof_on = false;
   std::vector<mag::ProfRec> prof;
   std::vector<hipEvent_t> ev_pool;

@@ -225,7 +225,7 @@ __global__ void __launch_bounds__((ColShape<NY, T>::THREADS))
   if (it->done) return;
   using CS = ColShape<NY, T>;
   constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NY>::RMAX;
-  extern __shared__ unsigned char smem_raw[];
+  HIP_DYNAMIC_SHARED(unsigned char, smem_raw)
   T *lre = reinterpret_cast<T *>(smem_raw), *lim = lre + NY * P;
   const int pcol = threadIdx.x % P, j = threadIdx.x / P;
   const int col = blockIdx.x * P + pcol;
@@ -494,6 +494,7 @@ static int film_observe_t(mag_ctx *c, const double *state, double t, double *hz,
     if ((rc = film_col<T>(c, 1))) return rc;
     if ((rc = film_inv<T, 2>(c, nullptr, hz, he[2], &nblk, K_MISC))) return rc;
   }
+  ProfScope ps(c, K_MISC);
   if (j) hipLaunchKernelGGL(film_current, dim3(nb), dim3(256), 0, c->stream, state, j, G.nx, G.ny, G.idx, G.idy);
   // m_z = sum g dx dy: fixed-order two-level sum
   hipLaunchKernelGGL(sum_blocks, dim3(nb), dim3(256), 0, c->stream, state, n, c->d_part);

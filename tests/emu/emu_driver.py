@@ -1,0 +1,96 @@
+"""Run the CPU-emulated HIP library on small cases and compare with the
+oracle.  TEST INFRASTRUCTURE ONLY (run in a subprocess with libasan preloaded,
+see tests/test_emu_bounds.py)."""
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from tests._cases import bulk_case, film_case, make_oracle, rel_l2  # noqa: E402
+from paper_1801_04869_amd import _lib  # noqa: E402
+
+
+def load(path):
+    L = ctypes.CDLL(path)
+    for name, (res, args) in _lib.SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+def P(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def setup(L, case, prec, fixed=0, max_inner=100, tol=None):
+    h = ctypes.c_void_p()
+    assert L.mag_create(ctypes.byref(h), case["dim"], prec, None) == 0
+    nx, ny, nz = case["n"]
+    assert L.mag_set_grid(h, nx, ny, nz, *case["L"]) == 0, L.mag_last_error(h)
+    mat = np.ascontiguousarray(case["mat"], dtype=np.uint8)
+    assert L.mag_set_domain(h, P(mat)) == 0, L.mag_last_error(h)
+    jc = None if case["jc"] is None else np.ascontiguousarray(case["jc"])
+    assert L.mag_set_params(h, None if jc is None else P(jc), 1.0, case["nexp"], 1.0, case["rho_out"]) == 0
+    if tol is None:
+        tol = 2e-4 if case["dim"] == 2 else 1e-4
+    assert L.mag_set_solver(h, 0.7, tol, max_inner, fixed) == 0
+    f = case["field"]
+    d = (ctypes.c_double * 3)(*[float(v) for v in f["dir"]])
+    assert L.mag_set_field(h, f["kind"], d, f["amp"], f["omega"], f["rate"]) == 0
+    return h, (mat, jc)
+
+
+def run_rhs(L, h, state, t):
+    s = np.ascontiguousarray(state, dtype=np.float64)
+    out = np.zeros_like(s)
+    it = ctypes.c_int(0)
+    rc = L.mag_rhs(h, P(s), t, P(out), ctypes.byref(it))
+    return rc, it.value, out
+
+
+def main(path, which):
+    from oracle import bulk, film
+    L = load(path)
+    fails = 0
+    cases = []
+    if which in ("bulk", "all"):
+        cases += [("bulk", bulk_case(16, 16, 16, half=(0.55, 0.55, 0.55)), 0, 1),
+                  ("bulk", bulk_case(32, 16, 16, L=(4.0, 2.0, 2.0), half=(1.3, 0.6, 0.6), shift=(1, 0, -2),
+                                     jc_s=0.2), 1, 2),
+                  ("bulk-wrap", bulk_case(16, 16, 16, half=(0.55, 0.55, 0.55), shift=(8, 0, 0)), 0, 2)]
+    if which in ("film", "all"):
+        cases += [("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2),
+                  ("film", film_case(16, 32, L=(1.0, 2.0), kind="ring", rho_out=20.0), 1, 1)]
+    for name, case, prec, fixed in cases:
+        h, keep = setup(L, case, prec, fixed=fixed)
+        rc, it, out = run_rhs(L, h, case["state"], 0.2)
+        prob = make_oracle(case, fixed=fixed)
+        mod = film if case["dim"] == 2 else bulk
+        ref, rit, rst = mod.rhs(prob, case["state"], 0.2)
+        err = rel_l2(out, ref)
+        tol = 1e-10 if prec == 0 else 1e-4
+        ok = rc == 0 and it == fixed and err < tol
+        fails += not ok
+        print("%-10s n=%s prec=%d fixed=%d rc=%d it=%d rel-L2=%.3e %s" % (name, case["n"], prec, fixed, rc, it, err,
+                                                                         "ok" if ok else "FAIL"), flush=True)
+        # observables
+        m = (ctypes.c_double * 3)()
+        s = np.ascontiguousarray(case["state"])
+        nn = int(np.prod(case["n"]))
+        hz = np.zeros(nn)
+        jj = np.zeros(case["dim"] * nn)
+        rc = L.mag_observe(h, P(s), 0.3, P(hz), P(jj), m)
+        print("   observe rc=%d m=%s" % (rc, list(m)), flush=True)
+        L.mag_destroy(h)
+    print("EMU_DONE fails=%d" % fails, flush=True)
+    return fails
+
+
+if __name__ == "__main__":
+    sys.exit(1 if main(sys.argv[1], sys.argv[2] if len(sys.argv) > 2 else "all") else 0)
