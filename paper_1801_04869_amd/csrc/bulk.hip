@@ -41,16 +41,32 @@ __device__ __forceinline__ int fold(int l, int b0, int b1, int n) {
 }
 
 // ------------------------------------------------------------ stencil pass
+// All grids are one-dimensional with 256 threads per block; box indices use
+// 32-bit arithmetic (the host checks that the box holds fewer than 2^31 points).
+constexpr int kBlk = 256;
+
+struct BoxIdx {
+  int lx, ly, lz;
+};
+__device__ __forceinline__ BoxIdx box_index(int tid, int bx, int by) {
+  BoxIdx b;
+  b.lx = tid % bx;
+  const int t = tid / bx;
+  b.ly = t % by;
+  b.lz = t / by;
+  return b;
+}
+
 // j = curl h on the faces of the extended box [b0-1, b1+1] (double arithmetic
 // from the double state, stored in T).
 template <typename T>
-__global__ void __launch_bounds__(256) bulk_curl_box(const double *__restrict__ h, T *__restrict__ jb,
-                                                     BulkGeom g, int bx, int by, int bz) {
-  const long long nbox = (long long)bx * by * bz;
-  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlk) bulk_curl_box(const double *__restrict__ h, T *__restrict__ jb,
+                                                      BulkGeom g, int bx, int by, int bz) {
+  const int nbox = bx * by * bz;
+  const int tid = blockIdx.x * kBlk + threadIdx.x;
   if (tid >= nbox) return;
-  const int lx = (int)(tid % bx), ly = (int)((tid / bx) % by), lz = (int)(tid / ((long long)bx * by));
-  const int p = wrap(g.b0x - 1 + lx, g.nx), q = wrap(g.b0y - 1 + ly, g.ny), r = wrap(g.b0z - 1 + lz, g.nz);
+  const BoxIdx b = box_index(tid, bx, by);
+  const int p = wrap(g.b0x - 1 + b.lx, g.nx), q = wrap(g.b0y - 1 + b.ly, g.ny), r = wrap(g.b0z - 1 + b.lz, g.nz);
   const long long N = (long long)g.nx * g.ny * g.nz;
   const double *hx = h, *hy = h + N, *hz = h + 2 * N;
   auto at = [&](int pp, int qq, int rr) {
@@ -77,15 +93,16 @@ __device__ __forceinline__ T power_rho(T s, T jc, T e0, T nm1, T lmax) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) bulk_efield_box(const T *__restrict__ jb, T *__restrict__ eb,
-                                                       const uint8_t *__restrict__ mat,
-                                                       const T *__restrict__ jc, BulkGeom g, int bx,
-                                                       int by, int bz, T e0, T nm1, T rho_out, T lmax,
-                                                       int has_jc, T jc0) {
-  const long long nbox = (long long)bx * by * bz;
-  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlk) bulk_efield_box(const T *__restrict__ jb, T *__restrict__ eb,
+                                                        const uint8_t *__restrict__ mat,
+                                                        const T *__restrict__ jc, BulkGeom g, int bx,
+                                                        int by, int bz, T e0, T nm1, T rho_out, T lmax,
+                                                        int has_jc, T jc0) {
+  const int nbox = bx * by * bz;
+  const int tid = blockIdx.x * kBlk + threadIdx.x;
   if (tid >= nbox) return;
-  const int lx = (int)(tid % bx), ly = (int)((tid / bx) % by), lz = (int)(tid / ((long long)bx * by));
+  const BoxIdx b = box_index(tid, bx, by);
+  const int lx = b.lx, ly = b.ly, lz = b.lz;
   const T *jx = jb, *jy = jb + nbox, *jz = jb + 2 * nbox;
   const bool interior = lx > 0 && ly > 0 && lz > 0 && lx < bx - 1 && ly < by - 1 && lz < bz - 1;
   if (!interior) {
@@ -93,61 +110,59 @@ __global__ void __launch_bounds__(256) bulk_efield_box(const T *__restrict__ jb,
     return;
   }
   const int p = wrap(g.b0x - 1 + lx, g.nx), q = wrap(g.b0y - 1 + ly, g.ny), r = wrap(g.b0z - 1 + lz, g.nz);
-  auto L = [&](int a, int b, int c) { return ((long long)c * by + b) * bx + a; };
+  auto L = [&](int a, int bb, int cc) { return (cc * by + bb) * bx + a; };
   auto cell = [&](int pp, int qq, int rr) {
     return ((long long)wrap(rr, g.nz) * g.ny + wrap(qq, g.ny)) * g.nx + wrap(pp, g.nx);
   };
-  const long long o = L(lx, ly, lz);
+  const int o = tid;
   // neighbours of an a-face among b-faces: offsets {-1,0} along a, {0,+1} along b
   const T jxo = jx[o], jyo = jy[o], jzo = jz[o];
-  const T jy_at_x = (T)0.25 * (jy[L(lx - 1, ly, lz)] + jy[o] + jy[L(lx - 1, ly + 1, lz)] + jy[L(lx, ly + 1, lz)]);
-  const T jz_at_x = (T)0.25 * (jz[L(lx - 1, ly, lz)] + jz[o] + jz[L(lx - 1, ly, lz + 1)] + jz[L(lx, ly, lz + 1)]);
-  const T jx_at_y = (T)0.25 * (jx[L(lx, ly - 1, lz)] + jx[o] + jx[L(lx + 1, ly - 1, lz)] + jx[L(lx + 1, ly, lz)]);
-  const T jz_at_y = (T)0.25 * (jz[L(lx, ly - 1, lz)] + jz[o] + jz[L(lx, ly - 1, lz + 1)] + jz[L(lx, ly, lz + 1)]);
-  const T jx_at_z = (T)0.25 * (jx[L(lx, ly, lz - 1)] + jx[o] + jx[L(lx + 1, ly, lz - 1)] + jx[L(lx + 1, ly, lz)]);
-  const T jy_at_z = (T)0.25 * (jy[L(lx, ly, lz - 1)] + jy[o] + jy[L(lx, ly + 1, lz - 1)] + jy[L(lx, ly + 1, lz)]);
-  const T s[3] = {sqrt(jxo * jxo + jy_at_x * jy_at_x + jz_at_x * jz_at_x),
-                  sqrt(jyo * jyo + jx_at_y * jx_at_y + jz_at_y * jz_at_y),
-                  sqrt(jzo * jzo + jx_at_z * jx_at_z + jy_at_z * jy_at_z)};
-  const T jv[3] = {jxo, jyo, jzo};
+  const T jy_at_x = (T)0.25 * (jy[L(lx - 1, ly, lz)] + jyo + jy[L(lx - 1, ly + 1, lz)] + jy[L(lx, ly + 1, lz)]);
+  const T jz_at_x = (T)0.25 * (jz[L(lx - 1, ly, lz)] + jzo + jz[L(lx - 1, ly, lz + 1)] + jz[L(lx, ly, lz + 1)]);
+  const T jx_at_y = (T)0.25 * (jx[L(lx, ly - 1, lz)] + jxo + jx[L(lx + 1, ly - 1, lz)] + jx[L(lx + 1, ly, lz)]);
+  const T jz_at_y = (T)0.25 * (jz[L(lx, ly - 1, lz)] + jzo + jz[L(lx, ly - 1, lz + 1)] + jz[L(lx, ly, lz + 1)]);
+  const T jx_at_z = (T)0.25 * (jx[L(lx, ly, lz - 1)] + jxo + jx[L(lx + 1, ly, lz - 1)] + jx[L(lx + 1, ly, lz)]);
+  const T jy_at_z = (T)0.25 * (jy[L(lx, ly, lz - 1)] + jyo + jy[L(lx, ly + 1, lz - 1)] + jy[L(lx, ly + 1, lz)]);
+  const T s0 = sqrt(jxo * jxo + jy_at_x * jy_at_x + jz_at_x * jz_at_x);
+  const T s1 = sqrt(jyo * jyo + jx_at_y * jx_at_y + jz_at_y * jz_at_y);
+  const T s2 = sqrt(jzo * jzo + jx_at_z * jx_at_z + jy_at_z * jy_at_z);
   const long long c0 = cell(p, q, r);
   const uint8_t m0 = mat[c0];
-  const long long cn[3] = {cell(p - 1, q, r), cell(p, q - 1, r), cell(p, q, r - 1)};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const uint8_t m1 = mat[cn[a]];
-    T e = (T)0;
+  auto face_e = [&](long long cn, T s, T jv) -> T {
+    const uint8_t m1 = mat[cn];
     if (m0 == 1 && m1 == 1) {
-      const T jcf = has_jc ? (T)0.5 * (jc[c0] + jc[cn[a]]) : jc0;
-      e = power_rho(s[a], jcf, e0, nm1, lmax) * jv[a];
-    } else if (m0 != 0 && m1 != 0) {
-      e = rho_out * jv[a];
+      const T jcf = has_jc ? (T)0.5 * (jc[c0] + jc[cn]) : jc0;
+      return power_rho(s, jcf, e0, nm1, lmax) * jv;
     }
-    eb[o + a * nbox] = e;
-  }
+    if (m0 != 0 && m1 != 0) return rho_out * jv;
+    return (T)0;
+  };
+  eb[o] = face_e(cell(p - 1, q, r), s0, jxo);
+  eb[o + nbox] = face_e(cell(p, q - 1, r), s1, jyo);
+  eb[o + 2 * nbox] = face_e(cell(p, q, r - 1), s2, jzo);
 }
 
 // dh/dt = -curl^T e on inside edges (backward differences inside the box).
 template <typename T>
-__global__ void __launch_bounds__(256) bulk_hdot_in(const T *__restrict__ eb, T *__restrict__ H,
-                                                    const uint8_t *__restrict__ flags, BulkGeom g, int bx,
-                                                    int by, int bz) {
-  const long long nbox = (long long)bx * by * bz;
-  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlk) bulk_hdot_in(const T *__restrict__ eb, T *__restrict__ H,
+                                                     const uint8_t *__restrict__ flags, BulkGeom g, int bx,
+                                                     int by, int bz) {
+  const int nbox = bx * by * bz;
+  const int tid = blockIdx.x * kBlk + threadIdx.x;
   if (tid >= nbox) return;
-  const int lx = (int)(tid % bx), ly = (int)((tid / bx) % by), lz = (int)(tid / ((long long)bx * by));
+  const BoxIdx b = box_index(tid, bx, by);
+  const int lx = b.lx, ly = b.ly, lz = b.lz;
   if (lx == 0 || ly == 0 || lz == 0 || lx == bx - 1 || ly == by - 1 || lz == bz - 1) return;
   const int p = wrap(g.b0x - 1 + lx, g.nx), q = wrap(g.b0y - 1 + ly, g.ny), r = wrap(g.b0z - 1 + lz, g.nz);
   const long long N = (long long)g.nx * g.ny * g.nz;
   const long long gi = ((long long)r * g.ny + q) * g.nx + p;
   const uint8_t f = flags[gi];
   if (!(f & 0x38)) return;
-  auto L = [&](int a, int b, int c) {
-    return ((long long)fold(c, g.b0z, g.b1z, g.nz) * by + fold(b, g.b0y, g.b1y, g.ny)) * bx +
-           fold(a, g.b0x, g.b1x, g.nx);
+  auto L = [&](int a, int bb, int cc) {
+    return (fold(cc, g.b0z, g.b1z, g.nz) * by + fold(bb, g.b0y, g.b1y, g.ny)) * bx + fold(a, g.b0x, g.b1x, g.nx);
   };
   const T *ex = eb, *ey = eb + nbox, *ez = eb + 2 * nbox;
-  const long long o = L(lx, ly, lz);
+  const int o = tid;
   if (f & 0x08) {
     const double v = (double(ez[o]) - double(ez[L(lx, ly - 1, lz)])) * g.idy -
                      (double(ey[o]) - double(ey[L(lx, ly, lz - 1)])) * g.idz;
@@ -167,9 +182,9 @@ __global__ void __launch_bounds__(256) bulk_hdot_in(const T *__restrict__ eb, T 
 
 // Free-space edges take dh_e/dt (first call or after a failed iteration).
 template <typename T>
-__global__ void __launch_bounds__(256) bulk_init_out(T *__restrict__ H, const uint8_t *__restrict__ flags,
-                                                     long long N, double h0, double h1, double h2) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlk) bulk_init_out(T *__restrict__ H, const uint8_t *__restrict__ flags,
+                                                      long long N, double h0, double h1, double h2) {
+  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
   if (i >= N) return;
   const uint8_t f = flags[i];
   if (!(f & 0x08)) H[i] = (T)h0;
@@ -178,21 +193,23 @@ __global__ void __launch_bounds__(256) bulk_init_out(T *__restrict__ H, const ui
 }
 
 // ------------------------------------------------------------ x_fwd
-// Rows (q, r) of the box, component blockIdx.y.  jdot = curl H on inside faces.
+// Rows (q, r) of the box for the three components: block b handles rows
+// (b % nblk) * P .. of component b / nblk.  jdot = curl H on inside faces.
 template <typename T, int M>
 __global__ void __launch_bounds__((RowShape<M, T>::THREADS))
     bulk_x_fwd(const T *__restrict__ H, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
-               const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN, BulkGeom g,
+               const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN, BulkGeom g, int nblk,
                const IterState *__restrict__ it) {
   if (it->done) return;
   using RS = RowShape<M, T>;
   constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX;
   constexpr int PITCH = RS::PITCH;
   __shared__ T lre[P * PITCH], lim[P * PITCH];
-  const int c = blockIdx.y;
+  const int c = blockIdx.x / nblk;
+  const int rb = blockIdx.x - c * nblk;
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
   const int nrow_y = g.b1y - g.b0y + 1, nrow_z = g.b1z - g.b0z + 1;
-  const int row = blockIdx.x * P + pr;
+  const int row = rb * P + pr;
   const bool active = row < nrow_y * nrow_z;
   const int q = g.b0y + (active ? row % nrow_y : 0), r = g.b0z + (active ? row / nrow_y : 0);
   const long long N = (long long)g.nx * g.ny * g.nz;
@@ -228,8 +245,9 @@ __global__ void __launch_bounds__((RowShape<M, T>::THREADS))
 
 // ------------------------------------------------------------ column transforms
 // In-place complex transforms of length NN along a strided axis.  Pencil
-// (col, plane): element i at base + plane*plane_stride + i*estride + col,
-// for col < ncols, planes [plane0, plane0 + nplanes), component blockIdx.z.
+// (col, plane) of component cc: element i at S + cc*comp_stride +
+// plane*plane_stride + i*estride + col, for col < ncols and planes
+// [plane0, plane0 + nplanes); block b covers component b / (ngrp*nplanes).
 // Inputs outside [lo, hi] are taken as zero (zero padding).
 template <typename T, int NN, int DIR>
 __global__ void __launch_bounds__((ColShape<NN, T>::THREADS))
@@ -243,10 +261,13 @@ __global__ void __launch_bounds__((ColShape<NN, T>::THREADS))
   T *lre = reinterpret_cast<T *>(smem_raw), *lim = lre + NN * P;
   const int pcol = threadIdx.x % P, j = threadIdx.x / P;
   const int ngrp = (ncols + P - 1) / P;
-  const int grp = blockIdx.x % ngrp, plane = plane0 + blockIdx.x / ngrp;
+  const int per_comp = ngrp * nplanes;
+  const int cc = blockIdx.x / per_comp;
+  const int bi = blockIdx.x - cc * per_comp;
+  const int grp = bi % ngrp, plane = plane0 + bi / ngrp;
   const int col = grp * P + pcol;
-  const bool active = col < ncols && plane < plane0 + nplanes;
-  cx<T> *base = S + blockIdx.z * comp_stride + (long long)plane * plane_stride + col;
+  const bool active = col < ncols;
+  cx<T> *base = S + (long long)cc * comp_stride + (long long)plane * plane_stride + (active ? col : 0);
   cx<T> v[RMAX];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
@@ -268,15 +289,32 @@ struct PhiTables {
   double inv_n;   // 1 / (nx ny nz)
 };
 
+// z pencils of P consecutive kx at one ky.  LDS holds the three transformed
+// components of the block's pencils (each thread keeps only one component in
+// registers at a time) plus one exchange area for the transforms.
+template <int NZ, typename T>
+struct ZShape {
+  static constexpr int TT = Plan<NZ>::TT;
+  static constexpr int PW = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int PL = pow2floor(kLdsBudget / (4 * NZ * 2 * (int)sizeof(T)));
+  static constexpr int PT = 1024 / TT;
+  static constexpr int P0 = PW < PL ? PW : PL;
+  static constexpr int P = P0 < PT ? P0 : PT;
+  static constexpr int THREADS = P * TT;
+  static constexpr int LDS_BYTES = 4 * NZ * P * 2 * (int)sizeof(T);
+};
+
 template <typename T, int NZ>
-__global__ void __launch_bounds__((ColShape<NZ, T>::THREADS))
+__global__ void __launch_bounds__((ZShape<NZ, T>::THREADS))
     bulk_z_phi(cx<T> *__restrict__ S, long long comp_stride, int kx, int ny, int lo, int hi,
                const cx<T> *__restrict__ tw, PhiTables tb, const IterState *__restrict__ it) {
   if (it->done) return;
-  using CS = ColShape<NZ, T>;
-  constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NZ>::RMAX;
+  using ZS = ZShape<NZ, T>;
+  constexpr int TT = ZS::TT, P = ZS::P, RMAX = Plan<NZ>::RMAX;
+  constexpr int SL = 2 * NZ * P;   // one slice (real then imaginary plane)
   HIP_DYNAMIC_SHARED(unsigned char, smem_raw)
-  T *lre = reinterpret_cast<T *>(smem_raw), *lim = lre + NZ * P;
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  T *xre = lds + 3 * SL, *xim = xre + NZ * P;   // exchange area
   const int pcol = threadIdx.x % P, j = threadIdx.x / P;
   const int ngrp = (kx + P - 1) / P;
   const int grp = blockIdx.x % ngrp, ky = blockIdx.x / ngrp;
@@ -285,50 +323,73 @@ __global__ void __launch_bounds__((ColShape<NZ, T>::THREADS))
   const long long estride = (long long)ny * kx;
   cx<T> *base = S + (long long)ky * kx + (active ? col : 0);
   auto lidx = [pcol](int i) { return i * P + pcol; };
-  cx<T> f[3][RMAX];
-#pragma unroll
+  cx<T> v[RMAX];
+  // forward transforms; each thread stores its own outputs (kz = j + rho TT)
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
     for (int rho = 0; rho < RMAX; ++rho) {
       const int i = j + rho * TT;
-      f[c][rho] = (active && i >= lo && i <= hi) ? base[c * comp_stride + (long long)i * estride]
-                                                 : cx<T>{(T)0, (T)0};
+      v[rho] = (active && i >= lo && i <= hi) ? base[c * comp_stride + (long long)i * estride]
+                                              : cx<T>{(T)0, (T)0};
     }
-    pencil_fft<NZ, -1>(f[c], j, lre, lim, lidx, tw);
+    pencil_fft<NZ, -1>(v, j, xre, xim, lidx, tw);
+    T *fre = lds + c * SL, *fim = fre + NZ * P;
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const int o = (j + rho * TT) * P + pcol;
+      fre[o] = v[rho].x;
+      fim[o] = v[rho].y;
+    }
   }
-  // Phi_x = (dy Fz - dz Fy) / |kappa|^2, cyclic; 1/N folded in.
+  // Phi_x = (dy Fz - dz Fy) / |kappa|^2, cyclic; 1/N folded in.  Only the
+  // thread's own entries are touched, so no barrier is needed.
   const double2 dxv = tb.dmx[active ? col : 0], dyv = tb.dmy[ky];
   const double k2xy = tb.k2x[active ? col : 0] + tb.k2y[ky];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
     const int kz = j + rho * TT;
+    const int o = kz * P + pcol;
     const double2 dzv = tb.dmz[kz];
     const double kk = k2xy + tb.k2z[kz];
     const double inv = kk > 0.0 ? tb.inv_n / kk : 0.0;
     const cx<T> dx = {(T)(dxv.x * inv), (T)(dxv.y * inv)};
     const cx<T> dy = {(T)(dyv.x * inv), (T)(dyv.y * inv)};
     const cx<T> dz = {(T)(dzv.x * inv), (T)(dzv.y * inv)};
-    const cx<T> Fx = f[0][rho], Fy = f[1][rho], Fz = f[2][rho];
-    f[0][rho] = cmul(dy, Fz) - cmul(dz, Fy);
-    f[1][rho] = cmul(dz, Fx) - cmul(dx, Fz);
-    f[2][rho] = cmul(dx, Fy) - cmul(dy, Fx);
+    const cx<T> Fx = {lds[o], lds[o + NZ * P]};
+    const cx<T> Fy = {lds[SL + o], lds[SL + o + NZ * P]};
+    const cx<T> Fz = {lds[2 * SL + o], lds[2 * SL + o + NZ * P]};
+    const cx<T> Px = cmul(dy, Fz) - cmul(dz, Fy);
+    const cx<T> Py = cmul(dz, Fx) - cmul(dx, Fz);
+    const cx<T> Pz = cmul(dx, Fy) - cmul(dy, Fx);
+    lds[o] = Px.x;
+    lds[o + NZ * P] = Px.y;
+    lds[SL + o] = Py.x;
+    lds[SL + o + NZ * P] = Py.y;
+    lds[2 * SL + o] = Pz.x;
+    lds[2 * SL + o + NZ * P] = Pz.y;
   }
-#pragma unroll
   for (int c = 0; c < 3; ++c) {
-    pencil_fft<NZ, +1>(f[c], j, lre, lim, lidx, tw);
+    const T *fre = lds + c * SL, *fim = fre + NZ * P;
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const int o = (j + rho * TT) * P + pcol;
+      v[rho] = {fre[o], fim[o]};
+    }
+    pencil_fft<NZ, +1>(v, j, xre, xim, lidx, tw);
     if (active) {
 #pragma unroll
-      for (int rho = 0; rho < RMAX; ++rho)
-        base[c * comp_stride + (long long)(j + rho * TT) * estride] = f[c][rho];
+      for (int rho = 0; rho < RMAX; ++rho) base[c * comp_stride + (long long)(j + rho * TT) * estride] = v[rho];
     }
   }
 }
 
 // ------------------------------------------------------------ x_inv + update
+// All rows of the three components: block b handles rows (b % nblk) * P .. of
+// component b / nblk and writes its partial sum to part[b].
 template <typename T, int M>
 __global__ void __launch_bounds__((RowShape<M, T>::THREADS))
     bulk_x_inv(T *__restrict__ H, const uint8_t *__restrict__ flags, const cx<T> *__restrict__ S,
-               const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN, BulkGeom g, double hd0,
+               const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN, BulkGeom g, int nblk, double hd0,
                double hd1, double hd2, double *__restrict__ part, const IterState *__restrict__ it) {
   if (it->done) return;
   using RS = RowShape<M, T>;
@@ -336,10 +397,11 @@ __global__ void __launch_bounds__((RowShape<M, T>::THREADS))
   constexpr int PITCH = RS::PITCH;
   __shared__ T lre[P * PITCH], lim[P * PITCH];
   __shared__ double red[RS::THREADS];
-  const int c = blockIdx.y;
+  const int c = blockIdx.x / nblk;
+  const int rb = blockIdx.x - c * nblk;
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
   const int nrows = g.ny * g.nz;
-  const int row = blockIdx.x * P + pr;
+  const int row = rb * P + pr;
   const bool active = row < nrows;
   const int q = active ? row % g.ny : 0, r = active ? row / g.ny : 0;
   const long long N = (long long)g.nx * g.ny * g.nz;
@@ -371,12 +433,12 @@ __global__ void __launch_bounds__((RowShape<M, T>::THREADS))
     }
   }
   const double s = block_sum<RS::THREADS>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) to_double_k(const T *__restrict__ src, double *__restrict__ dst, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlk) to_double_k(const T *__restrict__ src, double *__restrict__ dst, long long n) {
+  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
   if (i < n) dst[i] = (double)src[i];
 }
 
@@ -436,7 +498,7 @@ static int bulk_launch_col(mag_ctx *c, int dir, int n_axis, long long plane_stri
   MAG_SWITCH_N(n_axis, {
     using CS = ColShape<NN, T>;
     const int ngrp = (c->kx + CS::P - 1) / CS::P;
-    dim3 grid(ngrp * nplanes, 1, 3);
+    dim3 grid(3 * ngrp * nplanes);
     const size_t lds = (size_t)2 * NN * CS::P * sizeof(T);
     if (dir < 0)
       hipLaunchKernelGGL((col_fft<T, NN, -1>), grid, dim3(CS::THREADS), lds, c->stream, S, c->nspec,
@@ -464,9 +526,9 @@ static int bulk_iteration(mag_ctx *c, const double hd[3]) {
     const int nrows = (g.b1y - g.b0y + 1) * (g.b1z - g.b0z + 1);
     MAG_SWITCH_M(M, {
       using RS = RowShape<MM, T>;
-      dim3 grid((nrows + RS::P - 1) / RS::P, 3);
-      hipLaunchKernelGGL((bulk_x_fwd<T, MM>), grid, dim3(RS::THREADS), 0, c->stream, Hc, c->d_flags, S, twM,
-                         twN, g, c->d_it);
+      const int nb_rows = (nrows + RS::P - 1) / RS::P;
+      hipLaunchKernelGGL((bulk_x_fwd<T, MM>), dim3(3 * nb_rows), dim3(RS::THREADS), 0, c->stream, Hc, c->d_flags,
+                         S, twM, twN, g, nb_rows, c->d_it);
     });
   }
   // y forward on box z-planes, inputs y in the box
@@ -486,11 +548,10 @@ static int bulk_iteration(mag_ctx *c, const double hd[3]) {
     tb.k2z = sym + c->sym_off[5];
     tb.inv_n = 1.0 / (double)c->nnode;
     MAG_SWITCH_N(g.nz, {
-      using CS = ColShape<NN, T>;
-      const int ngrp = (g.kx + CS::P - 1) / CS::P;
-      const size_t lds = (size_t)2 * NN * CS::P * sizeof(T);
-      hipLaunchKernelGGL((bulk_z_phi<T, NN>), dim3(ngrp * g.ny), dim3(CS::THREADS), lds, c->stream, S,
-                         c->nspec, g.kx, g.ny, g.b0z, g.b1z, twZ, tb, c->d_it);
+      using ZS = ZShape<NN, T>;
+      const int ngrp = (g.kx + ZS::P - 1) / ZS::P;
+      hipLaunchKernelGGL((bulk_z_phi<T, NN>), dim3(ngrp * g.ny), dim3(ZS::THREADS), (size_t)ZS::LDS_BYTES,
+                         c->stream, S, c->nspec, g.kx, g.ny, g.b0z, g.b1z, twZ, tb, c->d_it);
     });
   }
   // y inverse on all planes
@@ -504,9 +565,8 @@ static int bulk_iteration(mag_ctx *c, const double hd[3]) {
     MAG_SWITCH_M(M, {
       using RS = RowShape<MM, T>;
       nblk = (nrows + RS::P - 1) / RS::P;
-      dim3 grid(nblk, 3);
-      hipLaunchKernelGGL((bulk_x_inv<T, MM>), grid, dim3(RS::THREADS), 0, c->stream, H, c->d_flags, S, twM,
-                         twN, g, hd[0], hd[1], hd[2], c->d_part, c->d_it);
+      hipLaunchKernelGGL((bulk_x_inv<T, MM>), dim3(3 * nblk), dim3(RS::THREADS), 0, c->stream, H, c->d_flags, S,
+                         twM, twN, g, nblk, hd[0], hd[1], hd[2], c->d_part, c->d_it);
     });
   }
   return run_finalize_stop(c, nblk * 3);
@@ -531,28 +591,28 @@ static int bulk_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   if (!c->warm_valid) {
     ProfScope ps(c, K_MISC);
     const long long N = c->nnode;
-    hipLaunchKernelGGL((bulk_init_out<T>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->stream, H,
+    hipLaunchKernelGGL((bulk_init_out<T>), dim3((unsigned)((N + kBlk - 1) / kBlk)), dim3(kBlk), 0, c->stream, H,
                        c->d_flags, N, hd[0], hd[1], hd[2]);
   }
   // stencil: j, e, dh_in on the box
   const int bx = c->boxn[0], by = c->boxn[1], bz = c->boxn[2];
   const long long nbox = c->boxvol;
   T *jb = reinterpret_cast<T *>(c->d_box), *eb = jb + 3 * nbox;
-  const unsigned nb = (unsigned)((nbox + 255) / 256);
+  const unsigned nb = (unsigned)((nbox + kBlk - 1) / kBlk);
   {
     ProfScope ps(c, K_BULK_CURL);
-    hipLaunchKernelGGL((bulk_curl_box<T>), dim3(nb), dim3(256), 0, c->stream, state, jb, g, bx, by, bz);
+    hipLaunchKernelGGL((bulk_curl_box<T>), dim3(nb), dim3(kBlk), 0, c->stream, state, jb, g, bx, by, bz);
   }
   {
     ProfScope ps(c, K_BULK_EFIELD);
     const double lmax = std::log(1e30) / (c->nexp - 1.0 > 1e-12 ? c->nexp - 1.0 : 1e-12);
-    hipLaunchKernelGGL((bulk_efield_box<T>), dim3(nb), dim3(256), 0, c->stream, jb, eb, c->d_mat,
+    hipLaunchKernelGGL((bulk_efield_box<T>), dim3(nb), dim3(kBlk), 0, c->stream, jb, eb, c->d_mat,
                        reinterpret_cast<const T *>(c->d_jc), g, bx, by, bz, (T)c->e0, (T)(c->nexp - 1.0),
                        (T)c->rho_out, (T)lmax, c->has_jc_map ? 1 : 0, (T)c->jc0);
   }
   {
     ProfScope ps(c, K_BULK_HDOT_IN);
-    hipLaunchKernelGGL((bulk_hdot_in<T>), dim3(nb), dim3(256), 0, c->stream, eb, H, c->d_flags, g, bx, by, bz);
+    hipLaunchKernelGGL((bulk_hdot_in<T>), dim3(nb), dim3(kBlk), 0, c->stream, eb, H, c->d_flags, g, bx, by, bz);
   }
   MAG_HIP(c, hipGetLastError());
   // inner iterations in blocks, one host poll per block
@@ -603,7 +663,7 @@ int bulk_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inne
 template <typename T>
 int run_to_double_t(mag_ctx *c, const void *src, double *dst, long long n) {
   ProfScope ps(c, K_MISC);
-  hipLaunchKernelGGL((to_double_k<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL((to_double_k<T>), dim3((unsigned)((n + kBlk - 1) / kBlk)), dim3(kBlk), 0, c->stream,
                      reinterpret_cast<const T *>(src), dst, n);
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
@@ -704,6 +764,7 @@ int bulk_domain(mag_ctx *c) {
   MAG_HIP(c, hipMemcpy(c->d_mat, m.data(), N, hipMemcpyHostToDevice));
   const size_t ts = c->prec == MAG_FP64 ? 8 : 4;
   c->boxvol = (long long)c->boxn[0] * c->boxn[1] * c->boxn[2];
+  if (3 * c->boxvol >= (1LL << 31)) return set_error(c, MAG_E_ARG, "sample box too large (%lld points)", c->boxvol);
   if (c->d_box) (void)hipFree(c->d_box);
   c->d_box = nullptr;
   MAG_HIP(c, hipMalloc(&c->d_box, 6 * c->boxvol * ts));

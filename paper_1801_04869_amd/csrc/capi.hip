@@ -11,6 +11,15 @@
 #include "ctx.h"
 #include "kern_common.h"
 
+// The 3D (bulk) path is compiled for gfx950 but held off the GPU: its first
+// GPU run ended in a memory fault whose cause has not been found (the CPU
+// emulation of the same sources stays in bounds and matches the FP64 oracle).
+// mag_set_grid refuses a 3D grid unless the build defines MAG_BULK_ENABLE,
+// which only the CPU emulation build does.
+#ifndef MAG_BULK_ENABLE
+#define MAG_BULK_ENABLE 0
+#endif
+
 namespace mag {
 
 int set_error(mag_ctx *c, int code, const char *fmt, ...) {
@@ -348,6 +357,9 @@ int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, doubl
   if (c->dim == 2 && nz != 1) return set_error(c, MAG_E_ARG, "nz must be 1 for a film");
   if (c->dim == 3 && !pow2_in(nz, 16, 2048)) return set_error(c, MAG_E_ARG, "nz must be a power of two in [16, 2048]");
   if (!(Lx > 0) || !(Ly > 0) || (c->dim == 3 && !(Lz > 0))) return set_error(c, MAG_E_ARG, "box half-lengths must be positive");
+  if (c->dim == 3 && !MAG_BULK_ENABLE)
+    return set_error(c, MAG_E_STATE,
+                     "the 3D path is disabled in this build (held off the GPU after an unexplained memory fault)");
   MAG_HIP(c, hipStreamSynchronize(c->stream));
   IterState *keep_it = c->d_it;
   c->d_it = nullptr;

@@ -20,7 +20,7 @@ def build(asan=True):
     if os.path.exists(OUT) and os.path.getmtime(OUT) > newest:
         return OUT
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-I", HERE,
-           "-Wno-ignored-attributes", "-Wno-attributes", "-fno-omit-frame-pointer"]
+           "-DMAG_BULK_ENABLE=1", "-Wno-ignored-attributes", "-Wno-attributes", "-fno-omit-frame-pointer"]
     if asan:
         cmd += ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
     cmd += ["-x", "c++"] + srcs + ["-o", OUT]

@@ -1,0 +1,45 @@
+"""CPU bounds check of the HIP sources: the library is compiled as host C++
+with AddressSanitizer and UndefinedBehaviorSanitizer against a small emulation
+of the HIP runtime (one CPU thread per work-item, real barriers), then run on
+small film and bulk cases and compared with the FP64 oracle.
+
+This is the only place the 3D path runs: it is held off the GPU (see the note
+in capi.hip), and the emulation build alone enables it."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def _libasan():
+    r = subprocess.run(["g++", "-print-file-name=libasan.so"], capture_output=True, text=True)
+    p = r.stdout.strip()
+    return p if p and os.path.isabs(p) and os.path.exists(p) else None
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("which", ["film", "bulk"])
+def test_emulated_kernels_in_bounds_and_match_oracle(which):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    asan = _libasan()
+    if asan is None:
+        pytest.skip("libasan not found")
+    sys.path.insert(0, ROOT)
+    from tests.emu import build_emu
+    lib = build_emu.build(asan=True)
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = asan
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    r = subprocess.run([sys.executable, os.path.join(HERE, "emu", "emu_driver.py"), lib, which],
+                       capture_output=True, text=True, env=env, cwd=ROOT, timeout=1200)
+    print(r.stdout[-4000:])
+    print(r.stderr[-4000:])
+    assert r.returncode == 0
+    assert "EMU_DONE fails=0" in r.stdout

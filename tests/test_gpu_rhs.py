@@ -23,9 +23,9 @@ TOL = {api.FP64: 1e-10, api.MIXED: 1e-4}
 
 # The first GPU run of the bulk tests faulted the GPU before any result came
 # back; the cause has not been shown on the CPU (the CPU emulation of the same
-# kernels is in bounds and matches the oracle), so the bulk cases stay off the
-# GPU until it is.
-BULK_OFF = pytest.mark.skip(reason="bulk path faulted on the GPU; cause not yet shown")
+# kernels is in bounds and matches the oracle, tests/test_emu_bounds.py), so
+# the library refuses 3D grids and the bulk cases stay off the GPU.
+BULK_OFF = pytest.mark.skip(reason="3D path held off the GPU after an unexplained GPU memory fault")
 
 
 def _gpu_rhs(ctx, state, t):
@@ -168,14 +168,21 @@ def _replay_steps(ctx, prob, case, mod, steps, t0):
     """Take the given step sizes on both sides with the same call order."""
     y = torch.from_numpy(np.ascontiguousarray(case["state"])).cuda()
     t = t0
-    k1, st = mod.rhs(prob, case["state"], t0)
+    from oracle import bs23
+    k1, _, st = mod.rhs(prob, case["state"], t0)
+    assert st == 0
     yo = case["state"].copy()
+
+    def f(tt, yy):
+        v, _, s = mod.rhs(prob, yy, tt)
+        return v, s
+
     for h in steps:
         t_new, dt_next, acc = ctx.step(y, t, h, rtol=1e-3, atol=1e-6)
-        f = lambda tt, yy: mod.rhs(prob, yy, tt)[::2]
-        ynew, k4, err, st = __import__("oracle.bs23", fromlist=["attempt"]).attempt(f, t, yo, h, k1)
-        from oracle import bs23
+        ynew, k4, err, st = bs23.attempt(f, t, yo, h, k1)
+        assert st == 0
         en = bs23.error_norm(err, yo, ynew, 1e-3, 1e-6)
+        print("step h=%g gpu accepted=%s oracle err norm=%.3f" % (h, acc, en), flush=True)
         assert acc == (en <= 1.0)
         if acc:
             yo, k1, t = ynew, k4, t + h
@@ -229,25 +236,41 @@ def test_film_integrate_matches_oracle():
 
 # ------------------------------------------------------------------ edge cases
 def test_argument_and_state_errors():
-    c = api.Context(3, api.FP64)
+    c = api.Context(2, api.FP64)
     with pytest.raises(api.MagError) as e:
-        c.set_grid(48, 32, 32, 1, 1, 1)
+        c.set_grid(48, 32, 1, 1, 1)
+    assert e.value.code == api.E_ARG
+    with pytest.raises(api.MagError) as e:
+        c.set_grid(32, 32, 2, 1, 1)
     assert e.value.code == api.E_ARG
     with pytest.raises(api.MagError) as e:
         c.set_domain(torch.zeros(8, dtype=torch.uint8, device="cuda"))
     assert e.value.code == api.E_STATE
-    c.set_grid(16, 16, 16, 1, 1, 1)
-    with pytest.raises(api.MagError) as e:
-        c.set_domain(torch.zeros(16, 16, 16, dtype=torch.uint8, device="cuda"))
-    assert e.value.code == api.E_ARG
-    bad = torch.full((16, 16, 16), 3, dtype=torch.uint8, device="cuda")
-    with pytest.raises(api.MagError) as e:
-        c.set_domain(bad)
-    assert e.value.code == api.E_ARG
-    s = torch.zeros(3, 16, 16, 16, dtype=torch.float64, device="cuda")
+    s = torch.zeros(32, 32, dtype=torch.float64, device="cuda")
     with pytest.raises(api.MagError) as e:
         c.rhs(s, 0.0, torch.empty_like(s))
     assert e.value.code == api.E_STATE
+    c.set_grid(32, 32, 1, 1, 1)
+    with pytest.raises(api.MagError) as e:
+        c.set_domain(torch.zeros(32, 32, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == api.E_ARG
+    bad = torch.full((32, 32), 3, dtype=torch.uint8, device="cuda")
+    with pytest.raises(api.MagError) as e:
+        c.set_domain(bad)
+    assert e.value.code == api.E_ARG
+    with pytest.raises(api.MagError) as e:
+        c.rhs(s, 0.0, torch.empty_like(s))
+    assert e.value.code == api.E_STATE
+
+
+def test_3d_grid_is_refused():
+    """The 3D path is held off the GPU: a 3D grid is refused before any 3D
+    allocation or launch."""
+    c = api.Context(3, api.FP64)
+    with pytest.raises(api.MagError) as e:
+        c.set_grid(32, 32, 32, 1, 1, 1)
+    assert e.value.code == api.E_STATE
+    assert "3D path is disabled" in str(e.value)
 
 
 @BULK_OFF
@@ -261,6 +284,24 @@ def test_nonfinite_state_is_reported_not_hung():
     with pytest.raises(api.MagError) as e:
         ctx.rhs(s, 0.2, out)
     assert e.value.code == api.E_NUMERIC
+
+
+def test_film_nonfinite_state_is_reported_not_hung():
+    case = film_case(64, 64, kind="rect")
+    ctx = make_gpu(case)
+    st = case["state"].copy()
+    st[32, 32] = np.nan
+    s = torch.from_numpy(st).cuda()
+    out = torch.empty_like(s)
+    with pytest.raises(api.MagError) as e:
+        ctx.rhs(s, 0.1, out)
+    assert e.value.code == api.E_NUMERIC
+    # the context stays usable after a numerical error
+    s2 = torch.from_numpy(case["state"]).cuda()
+    st2, it2 = ctx.rhs(s2, 0.1, out)
+    ref, rit, _ = film.rhs(make_oracle(case), case["state"], 0.1)
+    assert st2 == 0 and it2 == rit
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-10
 
 
 def test_not_converged_status_and_recovery():
@@ -287,3 +328,26 @@ def test_sample_touching_periodic_boundary():
     st, it, out = _gpu_rhs(ctx, case["state"], 0.2)
     ref, _, _ = bulk.rhs(prob, case["state"], 0.2)
     assert rel_l2(out, ref) < 1e-10
+
+
+# ------------------------------------------------------------------ full-size workload
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("mask", ["ring", "slot"])
+def test_film_2048_workload_matches_oracle(mask, prec):
+    """The benchmarked workload (1024^2-cell ring / slotted square in a 2048^2
+    grid, jc map, n = 30, rho_out = 500) at its full size, 4 inner iterations,
+    in the launch configuration the benchmark times: whole-field comparison."""
+    import bench
+    wl, mat, jc, g = bench.film_inputs(mask, 0.6)
+    ctx = bench.make_ctx("mixed" if prec == api.MIXED else "fp64", wl, mat, jc, fixed=4)
+    st, it, out = _gpu_rhs(ctx, g, 0.6)
+    from oracle.field import AppliedField
+    f = wl["field"]
+    prob = film.FilmProblem(2048, 2048, *wl["L"], mat, jc_cell=jc, n=wl["nexp"], rho_out=wl["rho_out"], lam=0.7,
+                            tol=2e-4, max_inner=4, fixed_iters=4,
+                            field=AppliedField(f["kind"], f["dir"], f["amp"], f["omega"], f["rate"]))
+    ref, rit, rst = film.rhs(prob, g, 0.6)
+    err = rel_l2(out, ref)
+    print("film-2048-%s prec %d: rel-L2 %.3e" % (mask, prec, err), flush=True)
+    assert st == 0 and rst == 0 and it == rit == 4
+    assert err < TOL[prec]
