@@ -208,8 +208,13 @@ def test_bulk_steps_match_oracle():
 
 
 def test_film_integrate_matches_oracle():
-    """Adaptive integration of the 64x64-cell square film (128^2 grid, n = 19,
-    h_e = t up to 0.5): same accepted steps, state, h_z, j and moment."""
+    """Free-running adaptive integration of the 64x64-cell square film (128^2
+    grid, n = 19, h_e = t up to 0.5) on both sides.  Each right-hand side is
+    converged only to the inner tolerance and the step controller feeds the
+    state back into the step size, so rounding differences grow along the run
+    (step sizes agree to 1e-15 at the start and drift apart later); this run
+    is compared at the integration tolerance, and the replayed-step test
+    below holds the FP64 bar."""
     from oracle import bs23
     case = film_case(128, 128, kind="rect", n=19.0)
     case["state"] = np.zeros_like(case["state"])
@@ -224,14 +229,42 @@ def test_film_integrate_matches_oracle():
 
     yo, to, hist = bs23.integrate(f, np.zeros(128 * 128), 0.0, 0.5)
     print("steps gpu", nsteps, "oracle", len(hist), flush=True)
-    assert nsteps == len(hist)
-    assert rel_l2(y.cpu().numpy().ravel(), yo) < 1e-9
+    assert abs(nsteps - len(hist)) <= 2
+    k = min(nsteps, len(hist), 20)
+    dts = np.array([r[1] for r in obs[:k]])
+    dto = np.array([h[1] for h in hist[:k]])
+    assert np.max(np.abs(dts - dto) / dto) < 1e-9
+    err = rel_l2(y.cpu().numpy().ravel(), yo)
+    print("final state rel-L2 %.3e" % err, flush=True)
+    assert err < 1e-5
     hz, j, m = ctx.observe(y, 0.5)
     rhz, (rjx, rjy), rm = film.observe(prob, yo.reshape(128, 128), 0.5)
-    assert rel_l2(hz.cpu().numpy(), rhz) < 1e-9
-    assert rel_l2(j.cpu().numpy(), np.stack([rjx, rjy])) < 1e-9
-    assert abs(m[2] - rm) < 1e-9 * abs(rm)
+    assert rel_l2(hz.cpu().numpy(), rhz) < 1e-5
+    assert rel_l2(j.cpu().numpy(), np.stack([rjx, rjy])) < 1e-4
+    assert abs(m[2] - rm) < 1e-5 * abs(rm)
     assert abs(obs[-1][0] - 0.5) < 1e-14
+
+
+def test_film_integrate_replayed_steps_match_oracle():
+    """The GPU takes the oracle's accepted step sizes one by one (mag_step with
+    the given dt) over the first 40 steps of the same run: FP64 bar."""
+    from oracle import bs23
+    case = film_case(128, 128, kind="rect", n=19.0)
+    prob = make_oracle(case)
+
+    def f(t, yy):
+        v, it, st = film.rhs(prob, yy.reshape(128, 128), t)
+        return (None if v is None else v.ravel()), st
+
+    _, _, hist = bs23.integrate(f, np.zeros(128 * 128), 0.0, 0.2)
+    steps = [h[1] for h in hist][:40]
+    prob.reset_warm_start()
+    case["state"] = np.zeros((128, 128))
+    ctx = make_gpu(case, api.FP64)
+    ygpu, yora = _replay_steps(ctx, prob, case, film, steps, 0.0)
+    err = rel_l2(ygpu, yora)
+    print("replayed %d steps: rel-L2 %.3e" % (len(steps), err), flush=True)
+    assert err < 1e-10
 
 
 # ------------------------------------------------------------------ edge cases
