@@ -84,7 +84,10 @@ void mag_destroy(mag_ctx *ctx);
 /* Uniform grid on D = [-Lx,Lx] x [-Ly,Ly] (x [-Lz,Lz]) with nx x ny (x nz)
  * nodes (Sec. 2.2 and 3.1).  nz must be 1 for dim 2.  Allocates the FFT and
  * iteration workspace.  Errors: MAG_E_ARG (sizes not powers of two in
- * [16, 2048], non-positive lengths), MAG_E_NOMEM. */
+ * [16, 2048], non-positive lengths), MAG_E_NOMEM; MAG_E_STATE for a 3D grid
+ * in GPU builds: the 3D path is compiled but disabled there (held off the GPU
+ * after an unexplained memory fault); only the CPU emulation build of the
+ * sources enables it. */
 int mag_set_grid(mag_ctx *ctx, int nx, int ny, int nz, double Lx, double Ly, double Lz);
 
 /* Material per cell, device uint8 array [nz][ny][nx] (nz = 1 in 2D):
