@@ -142,8 +142,23 @@ class Context:
         self._check(self._L.mag_reset_warm_start(self._h))
 
     # ---------------------------------------------------------- instrumentation
-    def prof_enable(self, on=True):
-        self._check(self._L.mag_prof_enable(self._h, 1 if on else 0))
+    def prof_enable(self, on=True, only=None):
+        """Record HIP events around kernel launches: all kernels, or only the
+        kernel named `only`."""
+        mode = 0
+        if on:
+            mode = 1 if only is None else 2 + self.kernel_id(only)
+        self._check(self._L.mag_prof_enable(self._h, mode))
+
+    def kernel_id(self, name):
+        k = 0
+        while True:
+            n = self._L.mag_prof_kernel_name(k)
+            if n is None:
+                raise KeyError(name)
+            if n.decode() == name:
+                return k
+            k += 1
 
     def prof_read(self):
         """{kernel name: (launches, total ms)} for kernels with recorded launches."""

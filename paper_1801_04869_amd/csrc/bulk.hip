@@ -586,8 +586,7 @@ static int bulk_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   is.fixed = c->fixed_iters;
   is.thr = c->tol * (hmag > 1.0 ? hmag : 1.0);
   is.inv_nout = c->nout > 0 ? 1.0 / (double)c->nout : 0.0;
-  *c->h_it = is;
-  MAG_HIP(c, hipMemcpyAsync(c->d_it, c->h_it, sizeof(IterState), hipMemcpyHostToDevice, c->stream));
+  if (int rc0 = run_iter_init(c, is)) return rc0;
   if (!c->warm_valid) {
     ProfScope ps(c, K_MISC);
     const long long N = c->nnode;
@@ -630,7 +629,6 @@ static int bulk_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
     c->cur_iter = -1;
     issued += nb_it;
     MAG_HIP(c, hipGetLastError());
-    MAG_HIP(c, hipMemcpyAsync(c->h_it, c->d_it, sizeof(IterState), hipMemcpyDeviceToHost, c->stream));
     MAG_HIP(c, hipStreamSynchronize(c->stream));
     if (c->h_it->done) {
       done = true;

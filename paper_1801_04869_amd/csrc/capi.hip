@@ -98,7 +98,7 @@ void prof_begin(mag_ctx *c, int kid, ProfRec *r) {
     fprintf(stderr, "[magfft] launch %s (iteration %d)\n", kNames[kid], c->cur_iter);
     fflush(stderr);
   }
-  if (!c->prof_on) return;
+  if (!c->prof_on || (c->prof_only >= 0 && kid != c->prof_only)) return;
   r->a = pool_get(c);
   r->b = pool_get(c);
   if (r->a) (void)hipEventRecord(r->a, c->stream);
@@ -148,17 +148,32 @@ __device__ __forceinline__ double fixed_order_sum(const double *__restrict__ par
   return block_sum<256>(s, sh);
 }
 
-__global__ void __launch_bounds__(256) finalize_stop_k(const double *__restrict__ part, int n, IterState *it) {
+// Stop test of the inner iteration.  The updated state is also written to
+// the context's pinned host mirror, which the host reads after synchronising
+// the stream (no separate device-to-host copy).
+__global__ void __launch_bounds__(256) finalize_stop_k(const double *__restrict__ part, int n, IterState *it,
+                                                       IterState *mirror) {
   if (it->done) return;
   __shared__ double sh[256];
   const double s = fixed_order_sum(part, n, sh);
   if (threadIdx.x == 0) {
-    const double r = s * it->inv_nout;
-    it->r = r;
-    it->iters += 1;
-    if (!isfinite(r)) it->done = 2;
-    else if (it->fixed > 0) it->done = it->iters >= it->fixed ? 1 : 0;
-    else it->done = r < it->thr ? 1 : 0;
+    IterState v = *it;
+    const double r = s * v.inv_nout;
+    v.r = r;
+    v.iters += 1;
+    if (!isfinite(r)) v.done = 2;
+    else if (v.fixed > 0) v.done = v.iters >= v.fixed ? 1 : 0;
+    else v.done = r < v.thr ? 1 : 0;
+    *it = v;
+    *mirror = v;
+  }
+}
+
+// Reset of the iteration state at the start of a right-hand side.
+__global__ void __launch_bounds__(64) iter_init_k(IterState *it, IterState *mirror, IterState v) {
+  if (threadIdx.x == 0) {
+    *it = v;
+    *mirror = v;
   }
 }
 
@@ -251,7 +266,14 @@ __global__ void scale_jc(const double *__restrict__ src, T *__restrict__ dst, do
 
 int run_finalize_stop(mag_ctx *c, int nparts) {
   ProfScope ps(c, K_FINALIZE);
-  hipLaunchKernelGGL(finalize_stop_k, dim3(1), dim3(256), 0, c->stream, c->d_part, nparts, c->d_it);
+  hipLaunchKernelGGL(finalize_stop_k, dim3(1), dim3(256), 0, c->stream, c->d_part, nparts, c->d_it, c->h_it);
+  return MAG_OK;
+}
+
+int run_iter_init(mag_ctx *c, const IterState &is) {
+  ProfScope ps(c, K_FINALIZE);
+  hipLaunchKernelGGL(iter_init_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->h_it, is);
+  MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
 
@@ -318,7 +340,8 @@ int mag_create(mag_ctx **out, int dim, int precision, void *hip_stream) {
   if (dim == 3) c->tol = 1e-4;
   const char *dbg = getenv("MAG_DEBUG_SYNC");
   c->debug_sync = dbg && dbg[0] == '1';
-  if (hipHostMalloc(&c->h_it, sizeof(IterState)) != hipSuccess) {
+  // coherent pinned memory: kernels write the iteration state straight into it
+  if (hipHostMalloc(&c->h_it, sizeof(IterState), hipHostMallocCoherent) != hipSuccess) {
     delete c;
     return MAG_E_HIP;
   }
@@ -713,7 +736,9 @@ int mag_prof_enable(mag_ctx *c, int on) {
   if (!c) return MAG_E_ARG;
   (void)hipStreamSynchronize(c->stream);
   prof_clear(c);
+  if (on < 0 || on >= 2 + K_COUNT) return set_error(c, MAG_E_ARG, "prof mode must be 0, 1 or 2 + kernel id");
   c->prof_on = on != 0;
+  c->prof_only = on >= 2 ? on - 2 : -1;
   return MAG_OK;
 }
 

@@ -127,6 +127,7 @@ struct mag_ctx {
   // instrumentation
   bool debug_sync = false;        // MAG_DEBUG_SYNC=1: synchronise and check after every launch
   bool prof_on = false;
+  int prof_only = -1;   // record only this kernel id (-1: all)
   std::vector<mag::ProfRec> prof;
   std::vector<hipEvent_t> ev_pool;
   int cur_iter = -1;
@@ -178,6 +179,7 @@ void field_hdot(const mag_ctx *c, double t, double hd[3]);
 
 // shared launches (capi.hip, bulk.hip)
 int run_finalize_stop(mag_ctx *c, int nparts);
+int run_iter_init(mag_ctx *c, const IterState &is);
 int run_finalize_mean(mag_ctx *c, int nparts, int which);
 int run_to_double(mag_ctx *c, const void *src, double *dst, long long n);
 

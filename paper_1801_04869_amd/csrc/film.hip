@@ -2,8 +2,9 @@
 // node/edge grid and the free-space iteration (10)-(12) of Prigozhin &
 // Sokolovsky, Sec. 2.
 //
-// Layouts (x fastest): g, dh/dt, G on nodes [ny][nx]; half spectrum [ny][kx],
-// kx = nx/2 + 1.  One inner iteration:
+// Layouts (x fastest): g, dh/dt, G on nodes [ny][nx]; half spectrum stored
+// transposed, [kx][ny] with kx = nx/2 + 1, so that every pass reads and
+// writes contiguous runs.  One inner iteration:
 //   rows_fwd(H)   apply the pending shift A on free-space nodes, R2C of H - dh_e
 //   cols(K1)      y transform, multiply by 2/|k| (and 1/N), inverse y transform
 //   rows_inv(G)   C2R -> G, per-block sums of G over free space
@@ -108,21 +109,58 @@ __global__ void __launch_bounds__(256) film_stencil(const double *__restrict__ g
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Row transforms.  MODE 0: H rows (apply shift A on free space, write back,
-// transform H - dh_e).  MODE 1: G rows (gdot = G - C, sums of |gdot| on free
-// space, transform gdot on free space).  MODE 2: rows of a double array.
+// Launch shape of the row transforms.  The half spectrum is stored
+// transposed, [kx][ny] (y fastest), so that the column pass reads contiguous
+// columns; a row block of P rows therefore writes (reads) P consecutive
+// complex values per wavenumber k, P chosen so that this run is at least 64
+// bytes.  The block's LDS holds either the FFT exchange of its P rows (pitch
+// M + M/16) or the transposed [M+1][P+1] tile of its output, one after the
+// other.
+template <int M, typename T>
+struct FilmRowShape {
+  static constexpr int TT = Plan<M>::TT;
+  static constexpr int PITCH = M + M / 16;
+  static constexpr int PMIN = 64 / (2 * (int)sizeof(T));
+  static constexpr int PT = 256 / TT > 0 ? 256 / TT : 1;
+  static constexpr int P = PT > PMIN ? PT : PMIN;
+  static constexpr int SP = P + 1;                    // tile pitch (complex entries per k)
+  static constexpr int XCH = 2 * P * PITCH;           // T entries of the FFT exchange
+  static constexpr int STG = 2 * (M + 1) * SP;        // T entries of the tile
+  static constexpr int LDS_T = XCH > STG ? XCH : STG;
+  static constexpr int THREADS = P * TT;
+  static_assert(THREADS <= 1024, "row block too large");
+  static_assert(LDS_T * sizeof(T) <= 150 * 1024, "row block LDS too large");
+};
+
+// Launch shape of the column pass: P contiguous columns of length NY per block.
+template <int NY, typename T>
+struct FilmColShape {
+  static constexpr int TT = Plan<NY>::TT;
+  static constexpr int P = 256 / TT > 0 ? 256 / TT : 1;
+  static constexpr int PITCH = NY + NY / 16;
+  static constexpr int LDS_T = 2 * P * PITCH;
+  static constexpr int THREADS = P * TT;
+  static_assert(LDS_T * sizeof(T) <= 150 * 1024, "column block LDS too large");
+};
+
+// Row transforms (real-to-complex along x, output transposed).
+// MODE 0: H rows (apply shift A on free space, write back, transform H - dh_e).
+// MODE 1: G rows (gdot = G - C, per-block sums of |gdot| on free space,
+//         transform gdot on free space).
+// MODE 2: rows of a double array.
 template <typename T, int M, int MODE>
-__global__ void __launch_bounds__((RowShape<M, T>::THREADS))
+__global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
                   cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
                   FilmGeom G, double hde, double *__restrict__ part, const IterState *__restrict__ it) {
   if (it->done) return;
-  using RS = RowShape<M, T>;
-  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH;
-  __shared__ T lre[P * PITCH], lim[P * PITCH];
+  using RS = FilmRowShape<M, T>;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ T lds[RS::LDS_T];
   __shared__ double red[RS::THREADS];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  const int q = blockIdx.x * P + pr;
+  const int q0 = blockIdx.x * P;
+  const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
   const double shift = MODE == 0 ? it->A : (MODE == 1 ? it->C : 0.0);
@@ -154,35 +192,87 @@ __global__ void __launch_bounds__((RowShape<M, T>::THREADS))
     }
     v[rho] = {val[0], val[1]};
   }
-  T *mre = lre + pr * PITCH, *mim = lim + pr * PITCH;
+  T *mre = lds + pr * PITCH, *mim = lds + P * PITCH + pr * PITCH;
   pencil_fft<M, -1>(v, j, mre, mim, [](int i) { return i + (i >> 4); }, twM);
-  r2c_finish<M>(v, j, mre, mim, twN, S + (long long)(active ? q : 0) * G.kx, active);
+  // Half spectrum of the real row from the packed transform Z:
+  // X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]), W = exp(-2 pi i / 2M).
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    mre[k] = v[rho].x;
+    mim[k] = v[rho].y;
+  }
+  __syncthreads();
+  cx<T> xk[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    const int km = (M - k) & (M - 1);
+    const cx<T> zk = v[rho];
+    const cx<T> zm = {mre[km], -mim[km]};
+    const cx<T> sum = zk + zm, dif = zk - zm;
+    const cx<T> wd = cmul(twN[k], dif);
+    xk[rho] = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
+  }
+  const cx<T> xm = {v[0].x - v[0].y, (T)0};   // X[M], meaningful in thread j = 0
+  __syncthreads();
+  cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
+  if (j == 0) tile[M * SP + pr] = xm;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
+    const int k = idx / P, r = idx % P;
+    if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
+  }
   if constexpr (MODE == 1) {
-    const double s = block_sum<RS::THREADS>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    const double sblk = block_sum<RS::THREADS>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sblk;
   }
 }
 
-// MODE 0: write G, sums of G over free space.  MODE 1: V -> H -= lambda V on
-// free space, sums of H - dh_e over D.  MODE 2: write hz = h_e + value (double).
+// Row transforms (complex-to-real along x, input transposed).
+// MODE 0: write G, per-block sums of G over free space.
+// MODE 1: V -> H -= lambda V on free space, per-block sums of H - dh_e over D.
+// MODE 2: write hz = h_e + value (double).
 template <typename T, int M, int MODE>
-__global__ void __launch_bounds__((RowShape<M, T>::THREADS))
+__global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
                   const cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
                   FilmGeom G, double hde, double lam, double *__restrict__ part,
                   const IterState *__restrict__ it) {
   if (it->done) return;
-  using RS = RowShape<M, T>;
-  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH;
-  __shared__ T lre[P * PITCH], lim[P * PITCH];
+  using RS = FilmRowShape<M, T>;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ T lds[RS::LDS_T];
   __shared__ double red[RS::THREADS];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  const int q = blockIdx.x * P + pr;
+  const int q0 = blockIdx.x * P;
+  const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
+  cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
+  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
+    const int k = idx / P, r = idx % P;
+    tile[k * SP + r] = q0 + r < G.ny ? S[(long long)k * G.ny + q0 + r] : cx<T>{(T)0, (T)0};
+  }
+  __syncthreads();
+  // Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]); the inverse
+  // transform of Z is x[2m] + i x[2m+1] times 2M.
   cx<T> v[RMAX];
-  c2r_start<M>(v, j, S + (long long)(active ? q : 0) * G.kx, twN, active);
-  T *mre = lre + pr * PITCH, *mim = lim + pr * PITCH;
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    const cx<T> a = tile[k * SP + pr];
+    const cx<T> b = tile[(M - k) * SP + pr];
+    const cx<T> sum = {a.x + b.x, a.y - b.y};
+    const cx<T> dif = {a.x - b.x, a.y + b.y};
+    const cx<T> wd = cmulc(dif, twN[k]);
+    v[rho] = {sum.x - wd.y, sum.y + wd.x};
+  }
+  if constexpr (Plan<M>::S == 1) __syncthreads();   // single-stage FFTs do not fence the tile
+  T *mre = lds + pr * PITCH, *mim = lds + P * PITCH + pr * PITCH;
   pencil_fft<M, +1>(v, j, mre, mim, [](int i) { return i + (i >> 4); }, twM);
   double acc = 0.0;
   if (active) {
@@ -211,32 +301,32 @@ __global__ void __launch_bounds__((RowShape<M, T>::THREADS))
     }
   }
   if constexpr (MODE != 2) {
-    const double s = block_sum<RS::THREADS>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    const double sblk = block_sum<RS::THREADS>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sblk;
   }
 }
 
-// Column pass: forward y transform, multiplier K(|k|) / N, inverse y transform.
-// which = 0: 2/|k| (eq. (7), 0 at k = 0); which = 1: |k|/2 (eq. (12)).
+// Column pass on the transposed spectrum: forward y transform of contiguous
+// columns, multiplier K(|k|) / N, inverse y transform.
+// which = 0: 2/|k| (eq. (7) solved for g, 0 at k = 0); which = 1: |k|/2 (eq. (12)).
 template <typename T, int NY>
-__global__ void __launch_bounds__((ColShape<NY, T>::THREADS))
+__global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     film_cols(cx<T> *__restrict__ S, int kx, const double *__restrict__ k2x, const double *__restrict__ k2y,
               double inv_n, int which, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
   if (it->done) return;
-  using CS = ColShape<NY, T>;
-  constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NY>::RMAX;
-  HIP_DYNAMIC_SHARED(unsigned char, smem_raw)
-  T *lre = reinterpret_cast<T *>(smem_raw), *lim = lre + NY * P;
-  const int pcol = threadIdx.x % P, j = threadIdx.x / P;
+  using CS = FilmColShape<NY, T>;
+  constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NY>::RMAX, PITCH = CS::PITCH;
+  __shared__ T lds[CS::LDS_T];
+  const int pcol = threadIdx.x / TT, j = threadIdx.x % TT;
   const int col = blockIdx.x * P + pcol;
   const bool active = col < kx;
-  cx<T> *base = S + (active ? col : 0);
-  auto lidx = [pcol](int i) { return i * P + pcol; };
+  cx<T> *base = S + (long long)(active ? col : 0) * NY;
   cx<T> v[RMAX];
 #pragma unroll
-  for (int rho = 0; rho < RMAX; ++rho)
-    v[rho] = active ? base[(long long)(j + rho * TT) * kx] : cx<T>{(T)0, (T)0};
-  pencil_fft<NY, -1>(v, j, lre, lim, lidx, tw);
+  for (int rho = 0; rho < RMAX; ++rho) v[rho] = active ? base[j + rho * TT] : cx<T>{(T)0, (T)0};
+  T *mre = lds + pcol * PITCH, *mim = lds + P * PITCH + pcol * PITCH;
+  auto lidx = [](int i) { return i + (i >> 4); };
+  pencil_fft<NY, -1>(v, j, mre, mim, lidx, tw);
   const double kxx = k2x[active ? col : 0];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
@@ -246,10 +336,10 @@ __global__ void __launch_bounds__((ColShape<NY, T>::THREADS))
     else mult = 0.5 * kk * inv_n;
     v[rho] = scale(v[rho], (T)mult);
   }
-  pencil_fft<NY, +1>(v, j, lre, lim, lidx, tw);
+  pencil_fft<NY, +1>(v, j, mre, mim, lidx, tw);
   if (active) {
 #pragma unroll
-    for (int rho = 0; rho < RMAX; ++rho) base[(long long)(j + rho * TT) * kx] = v[rho];
+    for (int rho = 0; rho < RMAX; ++rho) base[j + rho * TT] = v[rho];
   }
 }
 
@@ -347,7 +437,7 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, int kid) {
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, kid);
   FILM_SWITCH_M(G.nx / 2, {
-    using RS = RowShape<MM, T>;
+    using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
                        c->d_flags, f.S, f.twM, f.twN, G, hde, c->d_part, c->d_it);
@@ -361,7 +451,7 @@ static int film_inv(mag_ctx *c, T *X, double *xd, double hde, int *nblk_out, int
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, kid);
   FILM_SWITCH_M(G.nx / 2, {
-    using RS = RowShape<MM, T>;
+    using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     *nblk_out = nblk;
     hipLaunchKernelGGL((film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
@@ -376,10 +466,9 @@ static int film_col(mag_ctx *c, int which) {
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, K_FILM_COLS);
   FILM_SWITCH_N(G.ny, {
-    using CS = ColShape<NN, T>;
+    using CS = FilmColShape<NN, T>;
     const int nblk = (G.kx + CS::P - 1) / CS::P;
-    const size_t lds = (size_t)2 * NN * CS::P * sizeof(T);
-    hipLaunchKernelGGL((film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), lds, c->stream, f.S, G.kx, f.k2x, f.k2y,
+    hipLaunchKernelGGL((film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x, f.k2y,
                        1.0 / (double)c->nnode, which, f.twY, c->d_it);
   });
   return MAG_OK;
@@ -411,8 +500,7 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   is.fixed = c->fixed_iters;
   is.thr = c->tol * (std::fabs(hde) > 1.0 ? std::fabs(hde) : 1.0);
   is.inv_nout = c->nout > 0 ? 1.0 / (double)c->nout : 0.0;
-  *c->h_it = is;
-  MAG_HIP(c, hipMemcpyAsync(c->d_it, c->h_it, sizeof(IterState), hipMemcpyHostToDevice, c->stream));
+  if (int rc0 = run_iter_init(c, is)) return rc0;
   FilmLaw law;
   law.e0 = c->e0;
   law.nm1 = c->nexp - 1.0;
@@ -443,7 +531,6 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
     c->cur_iter = -1;
     issued += k;
     MAG_HIP(c, hipGetLastError());
-    MAG_HIP(c, hipMemcpyAsync(c->h_it, c->d_it, sizeof(IterState), hipMemcpyDeviceToHost, c->stream));
     MAG_HIP(c, hipStreamSynchronize(c->stream));
     if (c->h_it->done) {
       done = true;
@@ -486,8 +573,7 @@ static int film_observe_t(mag_ctx *c, const double *state, double t, double *hz,
   double he[3];
   field_h(c, t, he);
   IterState is{};
-  *c->h_it = is;
-  MAG_HIP(c, hipMemcpyAsync(c->d_it, c->h_it, sizeof(IterState), hipMemcpyHostToDevice, c->stream));
+  if (int rc0 = run_iter_init(c, is)) return rc0;
   int rc, nblk = 0;
   if (hz) {
     if ((rc = film_fwd<T, 2>(c, nullptr, state, 0.0, K_MISC))) return rc;

@@ -66,7 +66,8 @@ def main(path, which):
                   ("bulk-wrap", bulk_case(16, 16, 16, half=(0.55, 0.55, 0.55), shift=(8, 0, 0)), 0, 2)]
     if which in ("film", "all"):
         cases += [("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2),
-                  ("film", film_case(16, 32, L=(1.0, 2.0), kind="ring", rho_out=20.0), 1, 1)]
+                  ("film", film_case(16, 32, L=(1.0, 2.0), kind="ring", rho_out=20.0), 1, 1),
+                  ("film", film_case(128, 64, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2)]
     for name, case, prec, fixed in cases:
         h, keep = setup(L, case, prec, fixed=fixed)
         rc, it, out = run_rhs(L, h, case["state"], 0.2)

@@ -67,7 +67,8 @@ inline hipError_t hipMalloc(void *p, size_t n) {
 }
 template <typename T>
 inline hipError_t hipMallocAsync(T **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
-inline hipError_t hipHostMalloc(void *p, size_t n) { return hipMalloc(p, n); }
+#define hipHostMallocCoherent 0x40000000u
+inline hipError_t hipHostMalloc(void *p, size_t n, unsigned = 0) { return hipMalloc(p, n); }
 inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
 inline hipError_t hipFreeAsync(void *p, hipStream_t) { std::free(p); return hipSuccess; }
 inline hipError_t hipHostFree(void *p) { std::free(p); return hipSuccess; }
