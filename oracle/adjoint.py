@@ -1,0 +1,150 @@
+"""Vector-Jacobian products of the right-hand side, oracle form.  TEST
+INFRASTRUCTURE ONLY.
+
+The film right-hand side f(g, t) of Sec. 2.2 is the composition
+
+    g  --curl-bar (2)-->  j  --power law (3)-->  e  --minus curl, eq. (9)-->  dh_in
+       --iteration (10)-(12) on the free space-->  gdot.
+
+Writing x = dh - dh_e on all nodes, the iteration is linear in x:
+
+    start    x_out <- (warm start) ;  x <- S x
+    repeat   gdot = Q x ;  x <- S (x - lam P_out K2 P_out Q x)
+
+with Q = (I - 1 m_out^T) K1 (eq. (11) and the constant C that removes the
+free-space mean of gdot), P_out the free-space mask, K1 = F^{-1} 2/|k| F and
+K2 = F^{-1} |k|/2 F (real symmetric operators), m_out = 1_out / #out, and
+S = I - 1_out 1^T / #out the shift A of (10) that makes sum_D x = 0.  The
+warm start and dh_e only add constants, so the derivative of k evaluations of
+(11) with k - 1 updates (12) in between is
+
+    d gdot = Q B^(k-1) S E_in d(dh_in),   B = S (I - lam P_out K2 P_out Q),
+
+and its transpose applied to a cotangent y_bar is
+
+    x_bar = E_in^T S^T (B^T)^(k-1) Q^T y_bar,
+    B^T = (I - lam Q^T P_out K2 P_out) S^T,
+    Q^T z = K1 (z - m_out sum_D z),   S^T z = z - 1 (mean of z over free space).
+
+B^T leaves the film part of its argument untouched except for the
+accumulation coming from the free space, and its free-space part decays like
+the forward iteration's error, so the converged (fixed-point) adjoint is the
+same recursion run until the free-space part is negligible.
+
+The film part of x_bar is then pulled back through eq. (9), the power law and
+eq. (2), and through the edge jc = mean of the two cells to the per-cell map.
+"""
+import numpy as np
+
+from . import film
+from .film import shift
+
+OK, NOT_CONVERGED = 0, 1
+
+
+def _edge_partials(prob, g):
+    """Per edge: the current, its magnitude, e, de/dj_own and de/d(other-mean)
+    (the mean of the 4 nearest other-orientation components inside |j|)."""
+    jx, jy = film.sheet_current(prob, g)
+    jy_at_x = 0.25 * (shift(jy, 1, -1) + jy + shift(shift(jy, 1, -1), 0, 1) + shift(jy, 0, 1))
+    jx_at_y = 0.25 * (shift(jx, 0, -1) + jx + shift(shift(jx, 0, -1), 1, 1) + shift(jx, 1, 1))
+    out = []
+    for j, oth, jce, sc in ((jx, jy_at_x, prob.jc_xedge, prob.sc_xedge),
+                            (jy, jx_at_y, prob.jc_yedge, prob.sc_yedge)):
+        s = np.sqrt(j ** 2 + oth ** 2)
+        nm1 = prob.n - 1.0
+        rho_pl = (prob.e0 / jce) * (s / jce) ** nm1
+        pos = s > 0
+        s2 = np.where(pos, s * s, 1.0)
+        # e = rho(s) j with rho(s) = (e0/jc)(s/jc)^(n-1):
+        #   de/dj   = rho + j rho'(s) j/s = rho (1 + (n-1) j^2 / s^2)
+        #   de/doth = j rho'(s) oth/s    = rho (n-1) j oth / s^2
+        #   de/djc  = -n e / jc
+        a_pl = np.where(pos, rho_pl * (1.0 + nm1 * j * j / s2), (prob.e0 / jce) if nm1 == 0 else 0.0)
+        b_pl = np.where(pos, rho_pl * nm1 * j * oth / s2, 0.0)
+        e = np.where(sc, rho_pl * j, prob.rho_out * j)
+        a = np.where(sc, a_pl, prob.rho_out)
+        b = np.where(sc, b_pl, 0.0)
+        c = np.where(sc, -prob.n * e / jce, 0.0)
+        out.append((e, a, b, c))
+    return out
+
+
+def film_stencil_vjp(prob, g, hbar):
+    """Transpose of g -> dh_in (eqs. (2), (3), (9)) applied to hbar (zero off the
+    film).  Returns (g_bar, jc_cell_bar)."""
+    (ex, ax, bx, cx), (ey, ay, by, cy) = _edge_partials(prob, g)
+    dx, dy = prob.dx, prob.dy
+    # dh(p,q) = -[(e_y(p,q) - e_y(p-1,q))/dx - (e_x(p,q) - e_x(p,q-1))/dy]
+    ebar_y = (shift(hbar, 1, 1) - hbar) / dx
+    ebar_x = (hbar - shift(hbar, 0, 1)) / dy
+    # own-component and neighbour-mean parts of the power law
+    Bx = bx * ebar_x            # cotangent of jy_at_x on x-edges
+    By = by * ebar_y            # cotangent of jx_at_y on y-edges
+    jbar_x = ax * ebar_x + 0.25 * (By + shift(By, 0, 1) + shift(By, 1, -1) + shift(shift(By, 1, -1), 0, 1))
+    jbar_y = ay * ebar_y + 0.25 * (Bx + shift(Bx, 1, 1) + shift(Bx, 0, -1) + shift(shift(Bx, 1, 1), 0, -1))
+    # j_x(p,q) = (g(p,q+1) - g(p,q))/dy, j_y(p,q) = -(g(p+1,q) - g(p,q))/dx
+    gbar = (shift(jbar_x, 0, -1) - jbar_x) / dy + (jbar_y - shift(jbar_y, 1, -1)) / dx
+    # edge jc = mean of its two cells: x-edge (p,q) <- cells (p,q), (p-1,q); y-edge <- (p,q), (p,q-1)
+    Cx = cx * ebar_x
+    Cy = cy * ebar_y
+    jcbar = 0.5 * (Cx + shift(Cx, 1, 1)) + 0.5 * (Cy + shift(Cy, 0, 1))
+    return gbar, jcbar
+
+
+def film_iteration_vjp(prob, ybar, k=None):
+    """x_bar on the film nodes for the cotangent ybar of gdot.
+
+    k = number of evaluations of (11) in the forward (fixed-count form, the
+    exact transpose).  k = None: the converged form, B^T applied until the
+    mean free-space |S^T mu| is below prob.tol times the mean |Q^T ybar|, at most
+    prob.max_inner - 1 times.  Returns (xbar_in, count, status), count = the
+    number of evaluations of (11) the transposed recursion corresponds to."""
+    out = prob.out_node
+    nout = int(out.sum())
+    lam = prob.lam
+
+    def QT(z):
+        z = np.array(z, dtype=np.float64)
+        z[out] -= z.sum() / nout
+        return film.apply_multiplier(z, prob.K1)
+
+    def ST(z):
+        return z - z[out].mean()
+
+    mu = QT(ybar)
+    scale = np.abs(mu).mean()
+    steps = 0
+    status = OK
+    if k is not None:
+        for _ in range(k - 1):
+            nu = ST(mu)
+            w = film.apply_multiplier(np.where(out, nu, 0.0), prob.K2)
+            mu = nu - lam * QT(np.where(out, w, 0.0))
+            steps += 1
+    else:
+        while True:
+            nu = ST(mu)
+            if np.abs(nu[out]).mean() <= prob.tol * scale:
+                break
+            if steps >= prob.max_inner - 1:
+                status = NOT_CONVERGED
+                break
+            w = film.apply_multiplier(np.where(out, nu, 0.0), prob.K2)
+            mu = nu - lam * QT(np.where(out, w, 0.0))
+            steps += 1
+    xbar = ST(mu)
+    return np.where(prob.in_node, xbar, 0.0), steps + 1, status
+
+
+def film_rhs_vjp(prob, g, t, ybar, jc0=1.0):
+    """(g_bar, jc_map_bar, count, status) for the cotangent ybar of f(g, t).
+
+    With prob.fixed_iters > 0 the forward is that many evaluations of (11) and
+    this is its exact transpose; otherwise the converged form above.  The
+    cell jc is jc0 times the map, so jc_map_bar = jc0 * (cotangent of the cell jc).
+    t does not enter: dh_e/dt only shifts the iteration by constants."""
+    k = prob.fixed_iters if prob.fixed_iters > 0 else None
+    hbar, count, status = film_iteration_vjp(prob, ybar, k)
+    gbar, jcbar = film_stencil_vjp(prob, g, hbar)
+    return gbar, jc0 * jcbar, count, status
