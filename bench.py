@@ -136,8 +136,21 @@ def run_gpu(prec, wl, mat, jc, g, steps, warmup, t, fixed=0):
     dt = time.perf_counter() - t0
     prof_dom = ctx.prof_read()
     ctx.prof_enable(False)
+    # VJP of the same right-hand side (same fixed count), timed the same way
+    ybar = torch.ones_like(state)
+    gbar = torch.empty_like(state)
+    jcbar = torch.empty_like(state)
+    for _ in range(warmup):
+        assert ctx.rhs_vjp(state, t, ybar, gbar, jcbar) == 0, ctx.last_error()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        assert ctx.rhs_vjp(state, t, ybar, gbar, jcbar) == 0, ctx.last_error()
+    torch.cuda.synchronize()
+    dt_vjp = time.perf_counter() - t2
     res = dict(value=steps / dt, ms_per_step=1e3 * dt / steps, inner_iters=float(np.mean(iters)), prof=prof_all,
-               dominant=dominant, prof_dom=prof_dom[dominant], out=out.cpu().numpy())
+               dominant=dominant, prof_dom=prof_dom[dominant], out=out.cpu().numpy(),
+               vjp_ms=1e3 * dt_vjp / steps)
     ctx.close()
     return res
 
@@ -221,7 +234,8 @@ def main():
         if (mask, prec) == (a.mask, "mixed"):
             continue
         others["%s-%s" % (mask, prec)] = dict(value=round(r["value"], 3), ms_per_step=round(r["ms_per_step"], 4),
-                                              inner_iters=round(r["inner_iters"], 3))
+                                              inner_iters=round(r["inner_iters"], 3),
+                                              adjoint_forward_ratio=round(r["vjp_ms"] / r["ms_per_step"], 3))
     if others:
         line["other_lines"] = others
     if (a.mask, "fp64") in res:
@@ -231,7 +245,8 @@ def main():
         d = m["out"] - f64["out"]
         line["mixed_vs_fp64_rel_l2"] = float(np.linalg.norm(d) / max(np.linalg.norm(f64["out"]), 1e-300))
         line["kernels_fp64"] = kernel_table(f64["prof"], n, kx, ny, "fp64")
-    line["adjoint_forward_ratio"] = None
+    line["adjoint_forward_ratio"] = round(m["vjp_ms"] / m["ms_per_step"], 3)
+    line["adjoint_ms_per_rhs"] = round(m["vjp_ms"], 4)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, mat, jc, g, a.t, a.iters)
     line["host"] = dict(cpu=platform.processor() or platform.machine(), cpu_count=os.cpu_count(),

@@ -125,7 +125,7 @@ def film_iteration_vjp(prob, ybar, k=None):
     else:
         while True:
             nu = ST(mu)
-            if np.abs(nu[out]).mean() <= prob.tol * scale:
+            if np.abs(nu[out]).mean() < prob.tol * scale:
                 break
             if steps >= prob.max_inner - 1:
                 status = NOT_CONVERGED

@@ -846,8 +846,5 @@ int bulk_rhs_vjp(mag_ctx *c, const double *, double, const double *, double *, d
   return set_error(c, MAG_E_STATE, "bulk VJP not available yet");
 }
 
-int film_rhs_vjp(mag_ctx *c, const double *, double, const double *, double *, double *) {
-  return set_error(c, MAG_E_STATE, "film VJP not available yet");
-}
 
 }  // namespace mag

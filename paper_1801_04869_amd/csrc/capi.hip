@@ -184,7 +184,8 @@ __global__ void __launch_bounds__(256) finalize_mean_k(const double *__restrict_
   const double s = fixed_order_sum(part, n, sh);
   if (threadIdx.x == 0) {
     if (which == 0) it->C = s * it->inv_nout;
-    else it->A = s * it->inv_nout;
+    else if (which == 1) it->A = s * it->inv_nout;
+    else it->thr = s * it->sum0;   // stop threshold from a sum (sum0 holds the factor)
   }
 }
 
@@ -277,9 +278,9 @@ int run_iter_init(mag_ctx *c, const IterState &is) {
   return MAG_OK;
 }
 
-int run_finalize_mean(mag_ctx *c, int nparts, int which) {
+int run_finalize_mean(mag_ctx *c, int nparts, int which, int first) {
   ProfScope ps(c, K_FINALIZE);
-  hipLaunchKernelGGL(finalize_mean_k, dim3(1), dim3(256), 0, c->stream, c->d_part, nparts, c->d_it, which);
+  hipLaunchKernelGGL(finalize_mean_k, dim3(1), dim3(256), 0, c->stream, c->d_part + first, nparts, c->d_it, which);
   return MAG_OK;
 }
 

@@ -180,7 +180,9 @@ void field_hdot(const mag_ctx *c, double t, double hd[3]);
 // shared launches (capi.hip, bulk.hip)
 int run_finalize_stop(mag_ctx *c, int nparts);
 int run_iter_init(mag_ctx *c, const IterState &is);
-int run_finalize_mean(mag_ctx *c, int nparts, int which);
+// which: 0 -> C = sum * inv_nout, 1 -> A = sum * inv_nout, 2 -> thr = sum * sum0;
+// the partial sums start at d_part + first.
+int run_finalize_mean(mag_ctx *c, int nparts, int which, int first = 0);
 int run_to_double(mag_ctx *c, const void *src, double *dst, long long n);
 
 }  // namespace mag

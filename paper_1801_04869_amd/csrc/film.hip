@@ -148,6 +148,7 @@ struct FilmColShape {
 // MODE 1: G rows (gdot = G - C, per-block sums of |gdot| on free space,
 //         transform gdot on free space).
 // MODE 2: rows of a double array.
+// MODE 5: rows of a double array minus A on free space.
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
-  const double shift = MODE == 0 ? it->A : (MODE == 1 ? it->C : 0.0);
+  const double shift = (MODE == 0 || MODE == 5) ? it->A : (MODE == 1 ? it->C : 0.0);
   double acc = 0.0;
   cx<T> v[RMAX];
 #pragma unroll
@@ -186,6 +187,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           acc += fabs(gd);
           val[e] = (T)gd;
         }
+      } else if constexpr (MODE == 5) {
+        val[e] = (T)(xd[ro + p] - ((flags[ro + p] & 1) ? 0.0 : shift));
       } else {
         val[e] = (T)xd[ro + p];
       }
@@ -236,6 +239,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // MODE 0: write G, per-block sums of G over free space.
 // MODE 1: V -> H -= lambda V on free space, per-block sums of H - dh_e over D.
 // MODE 2: write hz = h_e + value (double).
+// Transposed iteration (the adjoint of (10)-(12)):
+// MODE 3: write the value on free space, 0 on the film; sums over free space.
+// MODE 4: X <- X - C - lambda value; sums of the new X over free space.
+// MODE 5: write the value; sums over free space, and sums of |value| over D
+//         (second half of part).
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -252,6 +260,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
+  const double cmean = MODE == 4 ? it->C : 0.0;
+  double acc2 = 0.0;
   cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
   for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
     const int k = idx / P, r = idx % P;
@@ -294,6 +304,17 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
             X[ro + p] = h;
           }
           acc += (double)h - hde;
+        } else if constexpr (MODE == 3) {
+          X[ro + p] = out ? val[e] : (T)0;
+          if (out) acc += (double)val[e];
+        } else if constexpr (MODE == 4) {
+          const T h = (T)((double)X[ro + p] - cmean - lam * (double)val[e]);
+          X[ro + p] = h;
+          if (out) acc += (double)h;
+        } else if constexpr (MODE == 5) {
+          X[ro + p] = val[e];
+          if (out) acc += (double)val[e];
+          acc2 += fabs((double)val[e]);
         } else {
           xd[ro + p] = hde + (double)val[e];
         }
@@ -303,6 +324,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   if constexpr (MODE != 2) {
     const double sblk = block_sum<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = sblk;
+  }
+  if constexpr (MODE == 5) {
+    __syncthreads();
+    const double sblk2 = block_sum<RS::THREADS>(acc2, red);
+    if (threadIdx.x == 0) part[(G.ny + P - 1) / P + blockIdx.x] = sblk2;
   }
 }
 
@@ -367,6 +393,120 @@ __global__ void __launch_bounds__(256) sum_blocks(const double *__restrict__ x, 
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const double s = block_sum<256>(i < n ? x[i] : 0.0, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------ adjoint stencil
+// Transpose of g -> dh_in (eqs. (2), (3), (9)).  For the x-edge (p, q+1/2)
+// and the y-edge (p+1/2, q) of node (p, q): the cotangent of e from the
+// film-node cotangent hbar = (mu - C) on inside nodes, then the partials of
+// e = rho(|j|) j: with s = |j| = sqrt(j_own^2 + oth^2),
+//   de/dj_own = rho (1 + (n-1) j_own^2 / s^2),   de/doth = rho (n-1) j_own oth / s^2,
+//   de/djc_edge = -n e / jc_edge   (superconducting edges; rho_out elsewhere).
+// Stored per edge (double): ebar de/dj_own, ebar de/doth, ebar de/djc.
+template <typename T>
+__device__ __forceinline__ void film_edge_vjp(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+                                              const T *__restrict__ jc, const FilmGeom &G, const FilmLaw &law,
+                                              int p, int q, int orient, double ebar, double *own, double *oth_bar,
+                                              double *jc_bar) {
+  const int nx = G.nx, ny = G.ny;
+  auto gv = [&](int pp, int qq) { return g[(long long)wrap(qq, ny) * nx + wrap(pp, nx)]; };
+  auto jxv = [&](int pp, int qq) { return (gv(pp, qq + 1) - gv(pp, qq)) * G.idy; };
+  auto jyv = [&](int pp, int qq) { return -(gv(pp + 1, qq) - gv(pp, qq)) * G.idx; };
+  double jo, oth;
+  const long long c0 = (long long)wrap(q, ny) * nx + wrap(p, nx);
+  long long c1;
+  if (orient == 0) {
+    jo = jxv(p, q);
+    oth = 0.25 * (jyv(p - 1, q) + jyv(p, q) + jyv(p - 1, q + 1) + jyv(p, q + 1));
+    c1 = (long long)wrap(q, ny) * nx + wrap(p - 1, nx);
+  } else {
+    jo = jyv(p, q);
+    oth = 0.25 * (jxv(p, q - 1) + jxv(p, q) + jxv(p + 1, q - 1) + jxv(p + 1, q));
+    c1 = (long long)wrap(q - 1, ny) * nx + wrap(p, nx);
+  }
+  if (mat[c0] == 1 && mat[c1] == 1) {
+    const T jt = (T)jo, ot = (T)oth;
+    const T s = sqrt(jt * jt + ot * ot);
+    const T jce = law.has_jc ? (T)0.5 * (jc[c0] + jc[c1]) : (T)law.jc0;
+    const T nm1 = (T)law.nm1;
+    T a, b;
+    if (s > (T)0) {
+      const T rho = film_rho(s, jce, (T)law.e0, nm1, (T)law.lmax);
+      const T is2 = (T)1 / (s * s);
+      a = rho * ((T)1 + nm1 * jt * jt * is2);
+      b = rho * nm1 * jt * ot * is2;
+      *jc_bar = ebar * (double)(-(nm1 + (T)1) * rho * jt / jce);
+    } else {
+      a = nm1 == (T)0 ? (T)law.e0 / jce : (T)0;
+      b = (T)0;
+      *jc_bar = 0.0;
+    }
+    *own = ebar * (double)a;
+    *oth_bar = ebar * (double)b;
+  } else {
+    *own = ebar * law.rho_out;
+    *oth_bar = 0.0;
+    *jc_bar = 0.0;
+  }
+}
+
+// Per node (p, q): the edge terms of its x-edge and y-edge, written to
+// E[0..5] planes: own_x, oth_x, jc_x, own_y, oth_y, jc_y.
+template <typename T>
+__global__ void __launch_bounds__(256) film_vjp_edges(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+                                                      const uint8_t *__restrict__ flags, const T *__restrict__ jc,
+                                                      const T *__restrict__ mu, FilmGeom G, FilmLaw law,
+                                                      double *__restrict__ E, const IterState *__restrict__ it) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = (long long)G.nx * G.ny;
+  if (i >= n) return;
+  const int p = (int)(i % G.nx), q = (int)(i / G.nx);
+  const double C = it->C;
+  auto hb = [&](int pp, int qq) {
+    const long long k = (long long)wrap(qq, G.ny) * G.nx + wrap(pp, G.nx);
+    return (flags[k] & 1) ? (double)mu[k] - C : 0.0;
+  };
+  const double h0 = hb(p, q);
+  // dh(p,q) = -[(e_y(p,q) - e_y(p-1,q))/dx - (e_x(p,q) - e_x(p,q-1))/dy]
+  const double ebx = (h0 - hb(p, q + 1)) * G.idy;
+  const double eby = (hb(p + 1, q) - h0) * G.idx;
+  double o, b, cj;
+  film_edge_vjp<T>(g, mat, jc, G, law, p, q, 0, ebx, &o, &b, &cj);
+  E[i] = o;
+  E[i + n] = b;
+  E[i + 2 * n] = cj;
+  film_edge_vjp<T>(g, mat, jc, G, law, p, q, 1, eby, &o, &b, &cj);
+  E[i + 3 * n] = o;
+  E[i + 4 * n] = b;
+  E[i + 5 * n] = cj;
+}
+
+// Per node: the edge-current cotangents (own part plus a quarter of the
+// neighbour-mean parts of the four other-orientation edges that average this
+// edge into their |j|), then g_bar by the transpose of eq. (2), and the cell
+// jc_bar from its four edges (edge jc = mean of two cells).
+__global__ void __launch_bounds__(256) film_vjp_gather(const double *__restrict__ E, double *__restrict__ gbar,
+                                                       double *__restrict__ jcbar, double jc0, FilmGeom G) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = (long long)G.nx * G.ny;
+  if (i >= n) return;
+  const int p = (int)(i % G.nx), q = (int)(i / G.nx);
+  auto at = [&](int pp, int qq) { return (long long)wrap(qq, G.ny) * G.nx + wrap(pp, G.nx); };
+  const double *own_x = E, *oth_x = E + n, *jcx = E + 2 * n, *own_y = E + 3 * n, *oth_y = E + 4 * n,
+               *jcy = E + 5 * n;
+  // x-edge (pp, qq) is averaged into the y-edges (pp, qq), (pp, qq+1), (pp-1, qq), (pp-1, qq+1)
+  auto jbx = [&](int pp, int qq) {
+    return own_x[at(pp, qq)] + 0.25 * (oth_y[at(pp, qq)] + oth_y[at(pp, qq + 1)] + oth_y[at(pp - 1, qq)] +
+                                       oth_y[at(pp - 1, qq + 1)]);
+  };
+  // y-edge (pp, qq) is averaged into the x-edges (pp, qq), (pp+1, qq), (pp, qq-1), (pp+1, qq-1)
+  auto jby = [&](int pp, int qq) {
+    return own_y[at(pp, qq)] + 0.25 * (oth_x[at(pp, qq)] + oth_x[at(pp + 1, qq)] + oth_x[at(pp, qq - 1)] +
+                                       oth_x[at(pp + 1, qq - 1)]);
+  };
+  // j_x(p,q) = (g(p,q+1) - g(p,q))/dy,  j_y(p,q) = -(g(p+1,q) - g(p,q))/dx
+  gbar[i] = (jbx(p, q - 1) - jbx(p, q)) * G.idy + (jby(p, q) - jby(p - 1, q)) * G.idx;
+  if (jcbar) jcbar[i] = jc0 * 0.5 * (jcx[i] + jcx[at(p + 1, q)] + jcy[i] + jcy[at(p, q + 1)]);
 }
 
 }  // namespace
@@ -599,6 +739,105 @@ static int film_observe_t(mag_ctx *c, const double *state, double t, double *hz,
 int film_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m) {
   return c->prec == MAG_FP64 ? film_observe_t<double>(c, state, t, hz, j, m)
                              : film_observe_t<float>(c, state, t, hz, j, m);
+}
+
+// ------------------------------------------------------------------ adjoint
+// Vector-Jacobian product of film_rhs: the transposed iteration
+//   mu = Q^T ybar;  repeat  nu = S^T mu,  mu = nu - lambda Q^T P_out K2 P_out nu
+// (Q^T z = K1 (z - m_out sum_D z), S^T z = z - mean_out z), stopped after the
+// forward's fixed count or when mean_out |nu| < tol mean_D |Q^T ybar|, then
+// the stencil transpose on the film part of S^T mu.
+template <typename T>
+static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, double *gbar, double *jcbar) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  const long long n = c->nnode;
+  const int nb = (int)((n + 255) / 256);
+  const size_t ts = sizeof(T);
+  const long long need = n * (long long)ts + 6 * n * (long long)sizeof(double);
+  if (c->adj_bytes < need) {
+    if (c->d_adj) (void)hipFree(c->d_adj);
+    c->d_adj = nullptr;
+    c->adj_bytes = 0;
+    MAG_HIP(c, hipMalloc(&c->d_adj, need));
+    c->adj_bytes = need;
+  }
+  double *E = reinterpret_cast<double *>(c->d_adj);
+  T *Z = reinterpret_cast<T *>(E + 6 * n);
+  T *Mu = f.G;   // the forward's G is scratch between calls
+  IterState is{};
+  is.fixed = c->fixed_iters;
+  is.inv_nout = c->nout > 0 ? 1.0 / (double)c->nout : 0.0;
+  is.sum0 = c->tol / (double)n;
+  int rc, nblk = 0;
+  if ((rc = run_iter_init(c, is))) return rc;
+  {
+    ProfScope ps(c, K_VJP);
+    hipLaunchKernelGGL(sum_blocks, dim3(nb), dim3(256), 0, c->stream, ybar, n, c->d_part);
+  }
+  if ((rc = run_finalize_mean(c, nb, 1))) return rc;                  // A = sum_D ybar / #out
+  if ((rc = film_fwd<T, 5>(c, nullptr, ybar, 0.0, K_VJP))) return rc;   // ybar - A on free space
+  if ((rc = film_col<T>(c, 0))) return rc;                             // K1
+  if ((rc = film_inv<T, 5>(c, Mu, nullptr, 0.0, &nblk, K_VJP))) return rc;
+  if ((rc = run_finalize_mean(c, nblk, 0))) return rc;                // C = mean_out mu
+  if ((rc = run_finalize_mean(c, nblk, 2, nblk))) return rc;          // thr = tol mean_D |mu|
+  MAG_HIP(c, hipGetLastError());
+  const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
+  int issued = 0;
+  int block = c->fixed_iters > 0 ? c->fixed_iters : (c->last_iters > 0 ? c->last_iters : 1);
+  bool done = false;
+  while (issued < kmax) {
+    const int k = block < kmax - issued ? block : kmax - issued;
+    for (int i = 0; i < k; ++i) {
+      c->cur_iter = issued + i;
+      if ((rc = film_fwd<T, 1>(c, Mu, nullptr, 0.0, K_VJP))) return rc;    // P_out (mu - C), sums |.|
+      if ((rc = run_finalize_stop(c, nblk))) return rc;
+      if ((rc = film_col<T>(c, 1))) return rc;                            // K2
+      if ((rc = film_inv<T, 3>(c, Z, nullptr, 0.0, &nblk, K_VJP))) return rc;
+      if ((rc = run_finalize_mean(c, nblk, 1))) return rc;                // A = sum_D z / #out
+      if ((rc = film_fwd<T, 0>(c, Z, nullptr, 0.0, K_VJP))) return rc;    // z - A on free space
+      if ((rc = film_col<T>(c, 0))) return rc;                            // K1
+      if ((rc = film_inv<T, 4>(c, Mu, nullptr, 0.0, &nblk, K_VJP))) return rc;
+      if ((rc = run_finalize_mean(c, nblk, 0))) return rc;                // C = mean_out mu
+    }
+    c->cur_iter = -1;
+    issued += k;
+    MAG_HIP(c, hipGetLastError());
+    MAG_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->h_it->done) {
+      done = true;
+      break;
+    }
+    block = 1;
+  }
+  const int used = c->h_it->iters;
+  prof_drop_after(c, used);
+  if (!done)
+    return set_error(c, MAG_NOT_CONVERGED, "transposed iteration not converged after %d iterations (r = %g)", used,
+                     c->h_it->r);
+  if (!std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C))
+    return set_error(c, MAG_E_NUMERIC, "non-finite value in the transposed iteration");
+  FilmLaw law;
+  law.e0 = c->e0;
+  law.nm1 = c->nexp - 1.0;
+  law.rho_out = c->rho_out;
+  law.lmax = std::log(1e30) / (c->nexp - 1.0 > 1e-12 ? c->nexp - 1.0 : 1e-12);
+  law.jc0 = c->jc0;
+  law.has_jc = c->has_jc_map ? 1 : 0;
+  {
+    ProfScope ps(c, K_VJP);
+    hipLaunchKernelGGL((film_vjp_edges<T>), dim3(nb), dim3(256), 0, c->stream, state, c->d_mat, c->d_flags,
+                       reinterpret_cast<const T *>(c->d_jc), Mu, G, law, E, c->d_it);
+    hipLaunchKernelGGL(film_vjp_gather, dim3(nb), dim3(256), 0, c->stream, E, gbar, jcbar, c->jc0, G);
+  }
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
+int film_rhs_vjp(mag_ctx *c, const double *state, double, const double *out_bar, double *state_bar,
+                 double *jc_bar) {
+  return c->prec == MAG_FP64 ? film_rhs_vjp_t<double>(c, state, out_bar, state_bar, jc_bar)
+                             : film_rhs_vjp_t<float>(c, state, out_bar, state_bar, jc_bar);
 }
 
 // ------------------------------------------------------------------ setup

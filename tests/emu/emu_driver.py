@@ -80,6 +80,20 @@ def main(path, which):
         fails += not ok
         print("%-10s n=%s prec=%d fixed=%d rc=%d it=%d rel-L2=%.3e %s" % (name, case["n"], prec, fixed, rc, it, err,
                                                                          "ok" if ok else "FAIL"), flush=True)
+        if case["dim"] == 2:
+            # vector-Jacobian product against the oracle's transpose
+            from oracle import adjoint
+            ybar = np.random.default_rng(7).standard_normal(case["state"].shape)
+            gb = np.zeros_like(ybar)
+            jb = np.zeros_like(ybar)
+            s_ = np.ascontiguousarray(case["state"])
+            rc = L.mag_rhs_vjp(h, P(s_), 0.2, P(ybar), P(gb), P(jb))
+            rg, rj, rcnt, rst = adjoint.film_rhs_vjp(prob, case["state"], 0.2, ybar)
+            e1 = rel_l2(gb, rg)
+            e2 = rel_l2(jb, rj) if case["jc"] is not None else 0.0
+            okv = rc == 0 and e1 < tol and e2 < tol
+            fails += not okv
+            print("   vjp rc=%d rel-L2 g=%.3e jc=%.3e %s" % (rc, e1, e2, "ok" if okv else "FAIL"), flush=True)
         # observables
         m = (ctypes.c_double * 3)()
         s = np.ascontiguousarray(case["state"])
