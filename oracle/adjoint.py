@@ -148,3 +148,73 @@ def film_rhs_vjp(prob, g, t, ybar, jc0=1.0):
     hbar, count, status = film_iteration_vjp(prob, ybar, k)
     gbar, jcbar = film_stencil_vjp(prob, g, hbar)
     return gbar, jc0 * jcbar, count, status
+
+
+# ------------------------------------------------------------------ time stepping
+def bs23_step_vjp(f, fvjp, t, y, h, ybar_new):
+    """Transpose of one Bogacki-Shampine step with a frozen step size h
+    (the step-size controller is treated as constant):
+
+        k1 = f(t, y),  k2 = f(t + h/2, y + h/2 k1),  k3 = f(t + 3h/4, y + 3h/4 k2)
+        y_new = y + h (2/9 k1 + 1/3 k2 + 4/9 k3)
+
+    f(t, y) -> value; fvjp(t, y, w) -> (y_bar, p_bar), the VJP of f at (t, y)
+    for the state and for a parameter vector.  Returns (y_bar, p_bar)."""
+    from .bs23 import A21, A32, B1, B2, B3, C2, C3
+    k1 = f(t, y)
+    y2 = y + (A21 * h) * k1
+    k2 = f(t + C2 * h, y2)
+    y3 = y + (A32 * h) * k2
+    kb1 = (h * B1) * ybar_new
+    kb2 = (h * B2) * ybar_new
+    kb3 = (h * B3) * ybar_new
+    yb3, pb3 = fvjp(t + C3 * h, y3, kb3)
+    kb2 = kb2 + (A32 * h) * yb3
+    yb2, pb2 = fvjp(t + C2 * h, y2, kb2)
+    kb1 = kb1 + (A21 * h) * yb2
+    yb1, pb1 = fvjp(t, y, kb1)
+    return ybar_new + yb3 + yb2 + yb1, pb3 + pb2 + pb1
+
+
+def film_pure_rhs(prob):
+    """f and its VJP for a film problem with every right-hand side started
+    from dh_e (no warm start), which makes f a function of (t, g) alone."""
+    def f(t, y):
+        prob.reset_warm_start()
+        v, it, st = film.rhs(prob, y, t)
+        if st != 0:
+            raise RuntimeError("right-hand side did not converge")
+        return v
+
+    def fvjp(t, y, w):
+        gb, jb, cnt, st = film_rhs_vjp(prob, y, t, w)
+        if st != 0:
+            raise RuntimeError("transposed iteration did not converge")
+        return gb, jb
+
+    return f, fvjp
+
+
+def film_trajectory_grad(prob, g0, t0, steps, obs_bar):
+    """Gradient of a loss on a replayed trajectory (fixed steps ``steps`` from
+    t0, every right-hand side started from dh_e).  obs_bar[i] is the cotangent
+    of the state after step i (None for no contribution).  Returns
+    (g0_bar, jc_map_bar, final state)."""
+    f, fvjp = film_pure_rhs(prob)
+    from .bs23 import A21, A32, B1, B2, B3, C2, C3
+    ys, ts = [np.array(g0, dtype=np.float64)], [float(t0)]
+    for h in steps:
+        y, t = ys[-1], ts[-1]
+        k1 = f(t, y)
+        k2 = f(t + C2 * h, y + (A21 * h) * k1)
+        k3 = f(t + C3 * h, y + (A32 * h) * k2)
+        ys.append(y + h * (B1 * k1 + B2 * k2 + B3 * k3))
+        ts.append(t + h)
+    ybar = np.zeros_like(ys[0])
+    pbar = np.zeros_like(ys[0])
+    for i in range(len(steps) - 1, -1, -1):
+        if obs_bar[i] is not None:
+            ybar = ybar + obs_bar[i]
+        ybar, pb = bs23_step_vjp(f, fvjp, ts[i], ys[i], steps[i], ybar)
+        pbar = pbar + pb
+    return ybar, pbar, ys[-1]

@@ -116,3 +116,58 @@ def test_film_iteration_vjp_is_transpose_of_linear_iteration():
     assert cnt == 3
     assert np.abs(xbar.ravel()[idx] - A.T @ y.ravel()).max() < 1e-12 * np.abs(A.T @ y.ravel()).max()
     assert np.all(xbar[~inn] == 0.0)
+
+
+def test_bs23_step_vjp_scalar_linear():
+    """For y' = a y (+ p as a source) one frozen step is y_new = R(ah) y with
+    R(z) = 1 + z + z^2/2 + z^3/6 (the pair is third order); its transpose is
+    the same factor."""
+    from oracle.adjoint import bs23_step_vjp
+    a, p = -3.0, 0.7
+    f = lambda t, y: a * y + p
+    fvjp = lambda t, y, w: (a * w, w)
+    h = 0.1
+    yb, pb = bs23_step_vjp(f, fvjp, 0.0, np.array([1.3]), h, np.array([1.0]))
+    z = a * h
+    assert abs(yb[0] - (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-15
+    # d y_new / d p: y_new = R y + p h (1 + z/2 + z^2/6)
+    assert abs(pb[0] - h * (1 + z / 2 + z * z / 6)) < 1e-15
+
+
+def test_film_trajectory_gradient_finite_differences():
+    """Gradient of L = <w1, y_2> + <w2, y_4> over 4 replayed BS23 steps of a
+    32 x 32 film (fixed inner count, no warm start) with respect to g0 and the
+    jc map, against central differences of the replayed forward."""
+    case = film_case(32, 32, kind="offrect", jc_s=0.2, n=5.0, rho_out=3.0)
+    prob = make_oracle(case, fixed=3)
+    g0 = case["state"]
+    steps = [2e-3, 3e-3, 1.5e-3, 2.5e-3]
+    rng = np.random.default_rng(21)
+    w1, w2 = rng.standard_normal(g0.shape), rng.standard_normal(g0.shape)
+    obs_bar = [None, w1, None, w2]
+    gb, jb, _ = adjoint.film_trajectory_grad(prob, g0, 0.1, steps, obs_bar)
+
+    def loss(g, jcm):
+        c2 = dict(case)
+        c2["jc"] = jcm
+        p2 = make_oracle(c2, fixed=3)
+        f, _ = adjoint.film_pure_rhs(p2)
+        from oracle.bs23 import A21, A32, B1, B2, B3, C2, C3
+        y, t, L = g, 0.1, 0.0
+        for i, h in enumerate(steps):
+            k1 = f(t, y)
+            k2 = f(t + C2 * h, y + (A21 * h) * k1)
+            k3 = f(t + C3 * h, y + (A32 * h) * k2)
+            y, t = y + h * (B1 * k1 + B2 * k2 + B3 * k3), t + h
+            if obs_bar[i] is not None:
+                L += np.vdot(obs_bar[i], y)
+        return L
+
+    v = rng.standard_normal(g0.shape)
+    u = rng.standard_normal(g0.shape)
+    eps = 1e-5
+    jc = case["jc"]
+    dL = (loss(g0 + eps * v, jc) - loss(g0 - eps * v, jc)) / (2 * eps)
+    assert abs(dL - np.vdot(gb, v)) < 1e-6 * abs(dL)
+    dL = (loss(g0, jc + eps * u) - loss(g0, jc - eps * u)) / (2 * eps)
+    assert abs(dL - np.vdot(jb, u)) < 1e-6 * abs(dL)
