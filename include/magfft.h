@@ -172,6 +172,30 @@ int mag_rhs_vjp(mag_ctx *ctx, const double *state, double t, const double *out_b
 /* Forget the warm start: the next mag_rhs starts from dh_e/dt. */
 int mag_reset_warm_start(mag_ctx *ctx);
 
+/* on = 0: every right-hand side starts the free-space iteration from dh_e/dt
+ * (no warm start), which makes f a function of (state, t) alone -- needed
+ * when a trajectory is recomputed for gradients; on = 1 (default): warm
+ * start from the previous call (Sec. 2.2). */
+int mag_set_warm_start(mag_ctx *ctx, int on);
+
+/* One Bogacki-Shampine step of exactly dt from (state, t), without error
+ * control (replay of an accepted step): state (device) advances in place.
+ * Returns MAG_NOT_CONVERGED (state unchanged) if an inner iteration fails. */
+int mag_step_fixed(mag_ctx *ctx, double *state, double t, double dt);
+
+/* Transpose of mag_step_fixed at (state, t, dt) with dt frozen: ybar
+ * (device, overwritten) = (d state_new / d state)^T ybar_new; jc_bar (device
+ * [nz][ny][nx], may be NULL) is ADDED the jc-map cotangent of the step.  The
+ * stages are recomputed (three right-hand sides) and pulled back with
+ * mag_rhs_vjp semantics.  ybar must not alias ybar_new or state. */
+int mag_step_vjp(mag_ctx *ctx, const double *state, double t, double dt, const double *ybar_new,
+                 double *ybar, double *jc_bar);
+
+/* Transpose of the map state -> h_z of mag_observe (h_e excluded):
+ * state_bar (device, overwritten) from hz_bar (device).  2D: the multiplier
+ * |k|/2 (Sec. 2.1) applied to hz_bar.  3D: MAG_E_STATE. */
+int mag_observe_vjp(mag_ctx *ctx, const double *hz_bar, double *state_bar);
+
 /* Text of the most recent error or status (never NULL). */
 const char *mag_last_error(const mag_ctx *ctx);
 

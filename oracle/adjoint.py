@@ -218,3 +218,9 @@ def film_trajectory_grad(prob, g0, t0, steps, obs_bar):
         ybar, pb = bs23_step_vjp(f, fvjp, ts[i], ys[i], steps[i], ybar)
         pbar = pbar + pb
     return ybar, pbar, ys[-1]
+
+
+def film_hz_vjp(prob, hz_bar):
+    """Transpose of g -> h_z = h_e + F^{-1}[|k|/2 F(g)] (Sec. 2.1): the
+    multiplier is real and even, so the operator is symmetric."""
+    return film.apply_multiplier(hz_bar, prob.K2)

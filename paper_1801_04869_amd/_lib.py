@@ -31,6 +31,10 @@ SIGNATURES = {
     "mag_observe": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, P_double]),
     "mag_rhs_vjp": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "mag_reset_warm_start": (c_int, [c_void_p]),
+    "mag_set_warm_start": (c_int, [c_void_p, c_int]),
+    "mag_step_fixed": (c_int, [c_void_p, c_void_p, c_double, c_double]),
+    "mag_step_vjp": (c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p]),
+    "mag_observe_vjp": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mag_last_error": (ctypes.c_char_p, [c_void_p]),
     "mag_prof_enable": (c_int, [c_void_p, c_int]),
     "mag_prof_read": (c_int, [c_void_p, c_int, P_int, P_double]),

@@ -78,6 +78,7 @@ class Context:
 
     def set_params(self, jc_map=None, jc0=1.0, n=19.0, e0=1.0, rho_out=1.0):
         self._check(self._L.mag_set_params(self._h, _ptr(jc_map, torch.float64), jc0, n, e0, rho_out))
+        self.params = (jc_map, jc0, n, e0, rho_out)
 
     def set_solver(self, lam=0.7, tol=None, max_inner=100, fixed_iters=0):
         if tol is None:
@@ -140,6 +141,23 @@ class Context:
 
     def reset_warm_start(self):
         self._check(self._L.mag_reset_warm_start(self._h))
+
+    def set_warm_start(self, on=True):
+        self._check(self._L.mag_set_warm_start(self._h, 1 if on else 0))
+
+    def step_fixed(self, state, t, dt):
+        """One step of exactly dt without error control (state advances in place)."""
+        return self._check(self._L.mag_step_fixed(self._h, _ptr(state, torch.float64), float(t), float(dt)),
+                           allow=(OK, NOT_CONVERGED))
+
+    def step_vjp(self, state, t, dt, ybar_new, ybar, jc_bar=None):
+        """ybar = (d step / d state)^T ybar_new; jc_bar += jc-map cotangent."""
+        return self._check(self._L.mag_step_vjp(self._h, _ptr(state, torch.float64), float(t), float(dt),
+                                                _ptr(ybar_new, torch.float64), _ptr(ybar, torch.float64),
+                                                _ptr(jc_bar, torch.float64)), allow=(OK, NOT_CONVERGED))
+
+    def observe_vjp(self, hz_bar, state_bar):
+        self._check(self._L.mag_observe_vjp(self._h, _ptr(hz_bar, torch.float64), _ptr(state_bar, torch.float64)))
 
     # ---------------------------------------------------------- instrumentation
     def prof_enable(self, on=True, only=None):

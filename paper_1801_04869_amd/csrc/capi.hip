@@ -202,6 +202,15 @@ __global__ void __launch_bounds__(256) rk_axpy_k(double *__restrict__ out, const
   out[i] = y[i] + h * s;
 }
 
+// out = a x + b y (y may be NULL); out may alias x or y.
+__global__ void __launch_bounds__(256) lincomb_k(double *out, double a, const double *x, double b, const double *y,
+                                                 long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double v = a * x[i] + (y ? b * y[i] : 0.0);
+  out[i] = v;
+}
+
 // per-block max of |h sum e_i k_i| / max(rtol max(|y|,|ynew|), atol); non-finite -> inf
 __global__ void __launch_bounds__(256) rk_errnorm_k(const double *__restrict__ k1, const double *__restrict__ k2,
                                                     const double *__restrict__ k3, const double *__restrict__ k4,
@@ -534,7 +543,14 @@ static int ready(mag_ctx *c) {
 }
 
 static int rhs_impl(mag_ctx *c, const double *state, double t, double *out, int *n_inner) {
+  if (!c->warm_enabled) c->warm_valid = false;
   return c->dim == 3 ? bulk_rhs(c, state, t, out, n_inner) : film_rhs(c, state, t, out, n_inner);
+}
+
+static int rhs_vjp_impl(mag_ctx *c, const double *state, double t, const double *out_bar, double *state_bar,
+                        double *jc_bar) {
+  return c->dim == 3 ? bulk_rhs_vjp(c, state, t, out_bar, state_bar, jc_bar)
+                     : film_rhs_vjp(c, state, t, out_bar, state_bar, jc_bar);
 }
 
 int mag_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner) {
@@ -552,6 +568,13 @@ int mag_reset_warm_start(mag_ctx *c) {
   CHECK_CTX(c);
   c->warm_valid = false;
   c->last_iters = 1;
+  return MAG_OK;
+}
+
+int mag_set_warm_start(mag_ctx *c, int on) {
+  CHECK_CTX(c);
+  c->warm_enabled = on != 0;
+  if (!c->warm_enabled) c->warm_valid = false;
   return MAG_OK;
 }
 
@@ -646,6 +669,85 @@ static int step_impl(mag_ctx *c, double *state, double *t, double *dt, double rt
   return MAG_OK;
 }
 
+static int launch_lincomb(mag_ctx *c, double *out, double a, const double *x, double b, const double *y,
+                          long long n) {
+  ProfScope ps(c, K_RK);
+  hipLaunchKernelGGL(lincomb_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, out, a, x, b, y, n);
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
+int mag_step_fixed(mag_ctx *c, double *state, double t, double dt) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state) return set_error(c, MAG_E_ARG, "NULL argument");
+  if (!(dt > 0) || !std::isfinite(t)) return set_error(c, MAG_E_ARG, "need dt > 0 and a finite t");
+  if ((rc = ensure_rk(c))) return rc;
+  c->fsal_valid = false;
+  double *k1 = rk_buf(c, 0), *k2 = rk_buf(c, 1), *k3 = rk_buf(c, 2), *yt = rk_buf(c, 4);
+  const double h = dt;
+  if ((rc = rhs_impl(c, state, t, k1, nullptr))) return rc;
+  if ((rc = launch_axpy(c, yt, state, k1, nullptr, nullptr, 1.0, 0, 0, 1, kA21 * h))) return rc;
+  if ((rc = rhs_impl(c, yt, t + kRkC2 * h, k2, nullptr))) return rc;
+  if ((rc = launch_axpy(c, yt, state, k2, nullptr, nullptr, 1.0, 0, 0, 1, kA32 * h))) return rc;
+  if ((rc = rhs_impl(c, yt, t + kRkC3 * h, k3, nullptr))) return rc;
+  if ((rc = launch_axpy(c, yt, state, k1, k2, k3, kB1, kB2, kB3, 3, h))) return rc;
+  return launch_lincomb(c, state, 1.0, yt, 0.0, nullptr, state_len(c));
+}
+
+// Transpose of mag_step_fixed at (state, t, dt): with y2 = y + h/2 k1 and
+// y3 = y + 3h/4 k2 recomputed,
+//   k3_bar = 4h/9 yb,  y3_bar = J(y3)^T k3_bar,
+//   k2_bar = h/3 yb + 3h/4 y3_bar,  y2_bar = J(y2)^T k2_bar,
+//   k1_bar = 2h/9 yb + h/2 y2_bar,  y1_bar = J(y)^T k1_bar,
+//   y_bar = yb + y3_bar + y2_bar + y1_bar,
+// and the jc-map cotangents of the three stages are added to jc_bar.
+int mag_step_vjp(mag_ctx *c, const double *state, double t, double dt, const double *ybar_new, double *ybar,
+                 double *jc_bar) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state || !ybar_new || !ybar) return set_error(c, MAG_E_ARG, "NULL argument");
+  if (ybar == ybar_new || ybar == state) return set_error(c, MAG_E_ARG, "ybar must not alias ybar_new or state");
+  if (!(dt > 0) || !std::isfinite(t)) return set_error(c, MAG_E_ARG, "need dt > 0 and a finite t");
+  if ((rc = ensure_rk(c))) return rc;
+  c->fsal_valid = false;
+  const long long n = state_len(c), nj = c->nnode;
+  double *A = rk_buf(c, 0), *Y2 = rk_buf(c, 1), *Y3 = rk_buf(c, 2), *D = rk_buf(c, 3), *E = rk_buf(c, 4);
+  const double h = dt;
+  int st;
+  // forward stages
+  if ((st = rhs_impl(c, state, t, A, nullptr))) return st;
+  if ((rc = launch_axpy(c, Y2, state, A, nullptr, nullptr, 1.0, 0, 0, 1, kA21 * h))) return rc;
+  if ((st = rhs_impl(c, Y2, t + kRkC2 * h, A, nullptr))) return st;
+  if ((rc = launch_axpy(c, Y3, state, A, nullptr, nullptr, 1.0, 0, 0, 1, kA32 * h))) return rc;
+  // reverse
+  if ((rc = launch_lincomb(c, ybar, 1.0, ybar_new, 0.0, nullptr, n))) return rc;
+  if ((rc = launch_lincomb(c, A, kB3 * h, ybar_new, 0.0, nullptr, n))) return rc;
+  if ((st = rhs_vjp_impl(c, Y3, t + kRkC3 * h, A, D, jc_bar ? E : nullptr))) return st;
+  if ((rc = launch_lincomb(c, ybar, 1.0, ybar, 1.0, D, n))) return rc;
+  if (jc_bar && (rc = launch_lincomb(c, jc_bar, 1.0, jc_bar, 1.0, E, nj))) return rc;
+  if ((rc = launch_lincomb(c, A, kB2 * h, ybar_new, kA32 * h, D, n))) return rc;
+  if ((st = rhs_vjp_impl(c, Y2, t + kRkC2 * h, A, D, jc_bar ? E : nullptr))) return st;
+  if ((rc = launch_lincomb(c, ybar, 1.0, ybar, 1.0, D, n))) return rc;
+  if (jc_bar && (rc = launch_lincomb(c, jc_bar, 1.0, jc_bar, 1.0, E, nj))) return rc;
+  if ((rc = launch_lincomb(c, A, kB1 * h, ybar_new, kA21 * h, D, n))) return rc;
+  if ((st = rhs_vjp_impl(c, state, t, A, D, jc_bar ? E : nullptr))) return st;
+  if ((rc = launch_lincomb(c, ybar, 1.0, ybar, 1.0, D, n))) return rc;
+  if (jc_bar && (rc = launch_lincomb(c, jc_bar, 1.0, jc_bar, 1.0, E, nj))) return rc;
+  return MAG_OK;
+}
+
+int mag_observe_vjp(mag_ctx *c, const double *hz_bar, double *state_bar) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!hz_bar || !state_bar) return set_error(c, MAG_E_ARG, "NULL argument");
+  if (c->dim == 3) return set_error(c, MAG_E_STATE, "3D observation transpose not available");
+  return film_hz_transpose(c, hz_bar, state_bar);
+}
+
 int mag_step(mag_ctx *c, double *state, double *t, double *dt, double rtol, double atol, int *accepted) {
   CHECK_CTX(c);
   int rc = ready(c);
@@ -728,9 +830,7 @@ int mag_rhs_vjp(mag_ctx *c, const double *state, double t, const double *out_bar
   int rc = ready(c);
   if (rc) return rc;
   if (!state || !out_bar || !state_bar) return set_error(c, MAG_E_ARG, "NULL argument");
-  c->fsal_valid = false;
-  return c->dim == 3 ? bulk_rhs_vjp(c, state, t, out_bar, state_bar, jc_bar)
-                     : film_rhs_vjp(c, state, t, out_bar, state_bar, jc_bar);
+  return rhs_vjp_impl(c, state, t, out_bar, state_bar, jc_bar);
 }
 
 int mag_prof_enable(mag_ctx *c, int on) {

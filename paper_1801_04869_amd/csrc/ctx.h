@@ -126,6 +126,7 @@ struct mag_ctx {
 
   // instrumentation
   bool debug_sync = false;        // MAG_DEBUG_SYNC=1: synchronise and check after every launch
+  bool warm_enabled = true;   // start each RHS from the previous free-space solution
   bool prof_on = false;
   int prof_only = -1;   // record only this kernel id (-1: all)
   std::vector<mag::ProfRec> prof;
@@ -166,6 +167,7 @@ int film_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inne
 int film_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m);
 int film_rhs_vjp(mag_ctx *c, const double *state, double t, const double *out_bar,
                  double *state_bar, double *jc_bar);
+int film_hz_transpose(mag_ctx *c, const double *hz_bar, double *state_bar);
 int bulk_alloc(mag_ctx *c);
 int bulk_domain(mag_ctx *c);
 int bulk_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner);

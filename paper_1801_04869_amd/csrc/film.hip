@@ -741,6 +741,25 @@ int film_observe(mag_ctx *c, const double *state, double t, double *hz, double *
                              : film_observe_t<float>(c, state, t, hz, j, m);
 }
 
+// Transpose of g -> h_z (post-processing of Sec. 2.1): the multiplier |k|/2 is
+// real and even, so the transpose is the same map without h_e.
+template <typename T>
+static int film_hz_transpose_t(mag_ctx *c, const double *hz_bar, double *state_bar) {
+  IterState is{};
+  if (int rc0 = run_iter_init(c, is)) return rc0;
+  int rc, nblk = 0;
+  if ((rc = film_fwd<T, 2>(c, nullptr, hz_bar, 0.0, K_MISC))) return rc;
+  if ((rc = film_col<T>(c, 1))) return rc;
+  if ((rc = film_inv<T, 2>(c, nullptr, state_bar, 0.0, &nblk, K_MISC))) return rc;
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
+int film_hz_transpose(mag_ctx *c, const double *hz_bar, double *state_bar) {
+  return c->prec == MAG_FP64 ? film_hz_transpose_t<double>(c, hz_bar, state_bar)
+                             : film_hz_transpose_t<float>(c, hz_bar, state_bar);
+}
+
 // ------------------------------------------------------------------ adjoint
 // Vector-Jacobian product of film_rhs: the transposed iteration
 //   mu = Q^T ybar;  repeat  nu = S^T mu,  mu = nu - lambda Q^T P_out K2 P_out nu
