@@ -118,31 +118,47 @@ __device__ __forceinline__ void dft(cx<T>* v) {
 }
 
 // ---------------------------------------------------------------- plans
+// A plan lists the radices of the stages (at most 4); RMAX is the largest and
+// sets how many values each thread holds.  Plan<N> favours radix 16 (fewest
+// LDS exchanges); Plan8<N> caps the radix at 8 (fewer registers per thread,
+// more threads per pencil).
 template <int N>
 struct Plan;
-#define MAG_PLAN(N_, S_, RMAX_, R0, R1, R2)                  \
+template <int N>
+struct Plan8;
+#define MAG_PLAN(NAME, N_, S_, RMAX_, R0, R1, R2, R3)         \
   template <>                                                \
-  struct Plan<N_> {                                          \
+  struct NAME<N_> {                                          \
     static constexpr int S = S_, RMAX = RMAX_;               \
-    static constexpr int R[3] = {R0, R1, R2};                \
+    static constexpr int R[4] = {R0, R1, R2, R3};            \
     static constexpr int TT = N_ / RMAX_;                    \
   };
-MAG_PLAN(8, 1, 8, 8, 1, 1)
-MAG_PLAN(16, 1, 16, 16, 1, 1)
-MAG_PLAN(32, 2, 8, 8, 4, 1)
-MAG_PLAN(64, 2, 8, 8, 8, 1)
-MAG_PLAN(128, 2, 16, 16, 8, 1)
-MAG_PLAN(256, 2, 16, 16, 16, 1)
-MAG_PLAN(512, 3, 8, 8, 8, 8)
-MAG_PLAN(1024, 3, 16, 16, 16, 4)
-MAG_PLAN(2048, 3, 16, 16, 16, 8)
-MAG_PLAN(4096, 3, 16, 16, 16, 16)
+MAG_PLAN(Plan, 8, 1, 8, 8, 1, 1, 1)
+MAG_PLAN(Plan, 16, 1, 16, 16, 1, 1, 1)
+MAG_PLAN(Plan, 32, 2, 8, 8, 4, 1, 1)
+MAG_PLAN(Plan, 64, 2, 8, 8, 8, 1, 1)
+MAG_PLAN(Plan, 128, 2, 16, 16, 8, 1, 1)
+MAG_PLAN(Plan, 256, 2, 16, 16, 16, 1, 1)
+MAG_PLAN(Plan, 512, 3, 8, 8, 8, 8, 1)
+MAG_PLAN(Plan, 1024, 3, 16, 16, 16, 4, 1)
+MAG_PLAN(Plan, 2048, 3, 16, 16, 16, 8, 1)
+MAG_PLAN(Plan, 4096, 3, 16, 16, 16, 16, 1)
+MAG_PLAN(Plan8, 8, 1, 8, 8, 1, 1, 1)
+MAG_PLAN(Plan8, 16, 2, 8, 8, 2, 1, 1)
+MAG_PLAN(Plan8, 32, 2, 8, 8, 4, 1, 1)
+MAG_PLAN(Plan8, 64, 2, 8, 8, 8, 1, 1)
+MAG_PLAN(Plan8, 128, 3, 8, 8, 8, 2, 1)
+MAG_PLAN(Plan8, 256, 3, 8, 8, 8, 4, 1)
+MAG_PLAN(Plan8, 512, 3, 8, 8, 8, 8, 1)
+MAG_PLAN(Plan8, 1024, 4, 8, 8, 8, 8, 2)
+MAG_PLAN(Plan8, 2048, 4, 8, 8, 8, 8, 4)
+MAG_PLAN(Plan8, 4096, 4, 8, 8, 8, 8, 8)
 #undef MAG_PLAN
 
-template <int N, int s>
+template <typename PL, int s>
 constexpr int plan_ns() {
   int ns = 1;
-  for (int i = 0; i < s; ++i) ns *= Plan<N>::R[i];
+  for (int i = 0; i < s; ++i) ns *= PL::R[i];
   return ns;
 }
 
@@ -150,17 +166,16 @@ constexpr int plan_ns() {
 // on exit.  lre/lim: this pencil's LDS scratch (real and imaginary planes),
 // element i at offset lidx(i).  tw: exp(-2 pi i m / N), m = 0..N-1.
 // Every thread of the block must call this (it contains barriers).
-template <int N, int DIR, typename T, typename LIdx>
+template <int N, int DIR, typename P = Plan<N>, typename T, typename LIdx>
 __device__ __forceinline__ void pencil_fft(cx<T>* v, int j, T* lre, T* lim, LIdx lidx,
                                            const cx<T>* __restrict__ tw) {
-  using P = Plan<N>;
   constexpr int RMAX = P::RMAX, TT = P::TT, S = P::S;
   if constexpr (S > 1) __syncthreads();   // LDS may still be read by a previous use
   static_for<0, S>([&](auto sI) {
     constexpr int s = decltype(sI)::value;
     constexpr int R = P::R[s];
     constexpr int U = RMAX / R;
-    constexpr int Ns = plan_ns<N, s>();
+    constexpr int Ns = plan_ns<P, s>();
     if constexpr (s > 0) {
       __syncthreads();
 #pragma unroll
@@ -194,6 +209,65 @@ __device__ __forceinline__ void pencil_fft(cx<T>* v, int j, T* lre, T* lim, LIdx
           lre[o] = a[r].x;
           lim[o] = a[r].y;
         }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u + r * U] = a[r];
+      }
+    }
+  });
+}
+
+// Powers w^r, r = 1..R-1, of one twiddle w by products of lower powers
+// (w^r = w^h w^(r-h), h the largest power of two below r): at most
+// log2(R) multiplications deep, so the rounding error stays a few ulp.
+template <int R, typename T>
+__device__ __forceinline__ void twiddle_powers(cx<T> w, cx<T>* wp) {
+  wp[1] = w;
+  static_for<2, R>([&](auto rI) {
+    constexpr int r = decltype(rI)::value;
+    constexpr int h = 1 << (ilog2(r) - ((r & (r - 1)) == 0 ? 1 : 0));
+    wp[r] = cmul(wp[h], wp[r - h]);
+  });
+}
+
+// Same transform as pencil_fft, with the LDS exchange holding interleaved
+// complex values (one access per element) and the inter-stage twiddles of a
+// thread formed from a single table entry per stage (twiddle_powers).
+template <int N, int DIR, typename P = Plan<N>, typename T, typename LIdx>
+__device__ __forceinline__ void pencil_fft_cx(cx<T>* v, int j, cx<T>* lds, LIdx lidx,
+                                              const cx<T>* __restrict__ tw) {
+  constexpr int RMAX = P::RMAX, TT = P::TT, S = P::S;
+  if constexpr (S > 1) __syncthreads();   // LDS may still be read by a previous use
+  static_for<0, S>([&](auto sI) {
+    constexpr int s = decltype(sI)::value;
+    constexpr int R = P::R[s];
+    constexpr int U = RMAX / R;
+    constexpr int Ns = plan_ns<P, s>();
+    if constexpr (s > 0) {
+      __syncthreads();
+#pragma unroll
+      for (int rho = 0; rho < RMAX; ++rho) v[rho] = lds[lidx(j + rho * TT)];
+      if constexpr (s < S - 1) __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = j + u * TT;
+      const int k = b & (Ns - 1);
+      cx<T> a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = v[u + r * U];
+      if constexpr (s > 0) {
+        constexpr int tstep = N / (Ns * R);
+        cx<T> wp[R];
+        twiddle_powers<R, T>(tw[k * tstep], wp);
+#pragma unroll
+        for (int r = 1; r < R; ++r) a[r] = (DIR < 0) ? cmul(a[r], wp[r]) : cmulc(a[r], wp[r]);
+      }
+      dft<R, DIR, T>(a);
+      if constexpr (s < S - 1) {
+        const int base = (b / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lidx(base + r * Ns)] = a[r];
       } else {
 #pragma unroll
         for (int r = 0; r < R; ++r) v[u + r * U] = a[r];

@@ -26,6 +26,8 @@ namespace mag {
 namespace {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
+__device__ __forceinline__ float inv_sqrt(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
 
 struct FilmGeom {
   int nx, ny, kx;
@@ -112,15 +114,17 @@ __global__ void __launch_bounds__(256) film_stencil(const double *__restrict__ g
 // Launch shape of the row transforms.  The half spectrum is stored
 // transposed, [kx][ny] (y fastest), so that the column pass reads contiguous
 // columns; a row block of P rows therefore writes (reads) P consecutive
-// complex values per wavenumber k, P chosen so that this run is at least 64
-// bytes.  The block's LDS holds either the FFT exchange of its P rows (pitch
+// complex values per wavenumber k, P chosen so that this run is at least 32
+// bytes.  Consecutive row blocks are placed on the same XCD (see
+// xcd_block) so that the runs of neighbouring blocks meet in one L2.  The block's LDS holds either the FFT exchange of its P rows (pitch
 // M + M/16) or the transposed [M+1][P+1] tile of its output, one after the
 // other.
 template <int M, typename T>
 struct FilmRowShape {
-  static constexpr int TT = Plan<M>::TT;
+  using PL = Plan8<M>;
+  static constexpr int TT = PL::TT;
   static constexpr int PITCH = M + M / 16;
-  static constexpr int PMIN = 64 / (2 * (int)sizeof(T));
+  static constexpr int PMIN = 32 / (2 * (int)sizeof(T));
   static constexpr int PT = 256 / TT > 0 ? 256 / TT : 1;
   static constexpr int P = PT > PMIN ? PT : PMIN;
   static constexpr int SP = P + 1;                    // tile pitch (complex entries per k)
@@ -132,10 +136,33 @@ struct FilmRowShape {
   static_assert(LDS_T * sizeof(T) <= 150 * 1024, "row block LDS too large");
 };
 
-// Launch shape of the column pass: P contiguous columns of length NY per block.
+// Partial sums passed between the passes of one iteration: `in` (nin values)
+// are summed by every block that needs the total (fixed order, so all agree),
+// `out` / `out2` receive one value per logical row block.  `iter` is the index
+// of the current evaluation of (11) for the stop decision in the column pass.
+struct Parts {
+  const double *in;
+  int nin;
+  double *out;
+  double *out2;
+  int iter;
+};
+
+// Work-groups are dealt to the 8 XCDs round-robin (hardware block i runs on
+// XCD i % 8).  Map them so that XCD x processes the contiguous logical range
+// [x nblk/8, (x+1) nblk/8) when nblk is a multiple of 8.
+__device__ __forceinline__ int xcd_block(int i, int nblk) {
+  if (nblk & 7) return i;
+  return (i & 7) * (nblk >> 3) + (i >> 3);
+}
+
+// Launch shape of the column pass: P contiguous columns of length NY per block,
+// radix at most 8 (8 values per thread keeps the register count low enough
+// for several blocks per compute unit).
 template <int NY, typename T>
 struct FilmColShape {
-  static constexpr int TT = Plan<NY>::TT;
+  using PL = Plan8<NY>;
+  static constexpr int TT = PL::TT;
   static constexpr int P = 256 / TT > 0 ? 256 / TT : 1;
   static constexpr int PITCH = NY + NY / 16;
   static constexpr int LDS_T = 2 * P * PITCH;
@@ -153,18 +180,28 @@ template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
                   cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
-                  FilmGeom G, double hde, double *__restrict__ part, const IterState *__restrict__ it) {
+                  FilmGeom G, double hde, Parts pp, IterState *__restrict__ it) {
   if (it->done) return;
   using RS = FilmRowShape<M, T>;
-  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH, SP = RS::SP;
-  __shared__ T lds[RS::LDS_T];
+  using PL = typename RS::PL;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[RS::THREADS];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  const int q0 = blockIdx.x * P;
+  const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
+  const int q0 = blk * P;
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
-  const double shift = (MODE == 0 || MODE == 5) ? it->A : (MODE == 1 ? it->C : 0.0);
+  // MODE 0: the shift A of (10) from the previous update's sums (or the
+  // stencil's, already reduced into it->A); MODE 1: C = free-space mean of G.
+  double shift = 0.0;
+  if constexpr (MODE == 0) shift = pp.in ? fixed_sum256<RS::THREADS>(pp.in, pp.nin, red) * it->inv_nout : it->A;
+  if constexpr (MODE == 1) {
+    shift = fixed_sum256<RS::THREADS>(pp.in, pp.nin, red) * it->inv_nout;
+    if (blockIdx.x == 0 && threadIdx.x == 0) it->C = shift;
+  }
+  if constexpr (MODE == 5) shift = it->A;
   double acc = 0.0;
   cx<T> v[RMAX];
 #pragma unroll
@@ -195,17 +232,13 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     }
     v[rho] = {val[0], val[1]};
   }
-  T *mre = lds + pr * PITCH, *mim = lds + P * PITCH + pr * PITCH;
-  pencil_fft<M, -1>(v, j, mre, mim, [](int i) { return i + (i >> 4); }, twM);
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
+  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
   // Half spectrum of the real row from the packed transform Z:
   // X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]), W = exp(-2 pi i / 2M).
   __syncthreads();
 #pragma unroll
-  for (int rho = 0; rho < RMAX; ++rho) {
-    const int k = j + rho * TT;
-    mre[k] = v[rho].x;
-    mim[k] = v[rho].y;
-  }
+  for (int rho = 0; rho < RMAX; ++rho) xch[j + rho * TT] = v[rho];
   __syncthreads();
   cx<T> xk[RMAX];
 #pragma unroll
@@ -213,7 +246,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     const int k = j + rho * TT;
     const int km = (M - k) & (M - 1);
     const cx<T> zk = v[rho];
-    const cx<T> zm = {mre[km], -mim[km]};
+    const cx<T> zm = conj(xch[km]);
     const cx<T> sum = zk + zm, dif = zk - zm;
     const cx<T> wd = cmul(twN[k], dif);
     xk[rho] = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
@@ -231,7 +264,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   }
   if constexpr (MODE == 1) {
     const double sblk = block_sum<RS::THREADS>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = sblk;
+    if (threadIdx.x == 0) pp.out[blk] = sblk;
   }
 }
 
@@ -248,15 +281,16 @@ template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
                   const cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
-                  FilmGeom G, double hde, double lam, double *__restrict__ part,
-                  const IterState *__restrict__ it) {
+                  FilmGeom G, double hde, double lam, Parts pp, const IterState *__restrict__ it) {
   if (it->done) return;
   using RS = FilmRowShape<M, T>;
-  constexpr int TT = RS::TT, P = RS::P, RMAX = Plan<M>::RMAX, PITCH = RS::PITCH, SP = RS::SP;
-  __shared__ T lds[RS::LDS_T];
+  using PL = typename RS::PL;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[RS::THREADS];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  const int q0 = blockIdx.x * P;
+  const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
+  const int q0 = blk * P;
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
@@ -281,9 +315,9 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     const cx<T> wd = cmulc(dif, twN[k]);
     v[rho] = {sum.x - wd.y, sum.y + wd.x};
   }
-  if constexpr (Plan<M>::S == 1) __syncthreads();   // single-stage FFTs do not fence the tile
-  T *mre = lds + pr * PITCH, *mim = lds + P * PITCH + pr * PITCH;
-  pencil_fft<M, +1>(v, j, mre, mim, [](int i) { return i + (i >> 4); }, twM);
+  if constexpr (PL::S == 1) __syncthreads();   // single-stage FFTs do not fence the tile
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
+  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
   double acc = 0.0;
   if (active) {
 #pragma unroll
@@ -323,12 +357,12 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   }
   if constexpr (MODE != 2) {
     const double sblk = block_sum<RS::THREADS>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = sblk;
+    if (threadIdx.x == 0) pp.out[blk] = sblk;
   }
   if constexpr (MODE == 5) {
     __syncthreads();
     const double sblk2 = block_sum<RS::THREADS>(acc2, red);
-    if (threadIdx.x == 0) part[(G.ny + P - 1) / P + blockIdx.x] = sblk2;
+    if (threadIdx.x == 0) pp.out2[blk] = sblk2;
   }
 }
 
@@ -338,11 +372,29 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 template <typename T, int NY>
 __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     film_cols(cx<T> *__restrict__ S, int kx, const double *__restrict__ k2x, const double *__restrict__ k2y,
-              double inv_n, int which, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
+              double inv_n, int which, const cx<T> *__restrict__ tw, Parts pp, IterState *__restrict__ it,
+              IterState *mirror) {
   if (it->done) return;
   using CS = FilmColShape<NY, T>;
-  constexpr int TT = CS::TT, P = CS::P, RMAX = Plan<NY>::RMAX, PITCH = CS::PITCH;
-  __shared__ T lds[CS::LDS_T];
+  using PL = typename CS::PL;
+  constexpr int TT = CS::TT, P = CS::P, RMAX = PL::RMAX, PITCH = CS::PITCH;
+  __shared__ __align__(16) T lds[CS::LDS_T];
+  if (pp.in) {
+    // Stop test of Sec. 2.3 on the residual sums of the previous pass: every
+    // block takes the same decision; block 0 records it.
+    __shared__ double red[CS::THREADS];
+    const double r = fixed_sum256<CS::THREADS>(pp.in, pp.nin, red) * it->inv_nout;
+    const int iters = pp.iter + 1;
+    const int fixed = it->fixed;
+    const int done = !isfinite(r) ? 2 : (fixed > 0 ? (iters >= fixed ? 1 : 0) : (r < it->thr ? 1 : 0));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      it->r = r;
+      it->iters = iters;
+      it->done = done;
+      *mirror = *it;
+    }
+    if (done) return;
+  }
   const int pcol = threadIdx.x / TT, j = threadIdx.x % TT;
   const int col = blockIdx.x * P + pcol;
   const bool active = col < kx;
@@ -350,19 +402,21 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   cx<T> v[RMAX];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) v[rho] = active ? base[j + rho * TT] : cx<T>{(T)0, (T)0};
-  T *mre = lds + pcol * PITCH, *mim = lds + P * PITCH + pcol * PITCH;
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
   auto lidx = [](int i) { return i + (i >> 4); };
-  pencil_fft<NY, -1>(v, j, mre, mim, lidx, tw);
-  const double kxx = k2x[active ? col : 0];
+  pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, tw);
+  // multiplier in the compute precision: |k|^2 = kx^2 + ky^2
+  const T kxx = (T)k2x[active ? col : 0];
+  const T c1 = (T)(2.0 * inv_n), c2 = (T)(0.5 * inv_n);
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
-    const double kk = sqrt(kxx + k2y[j + rho * TT]);
-    double mult;
-    if (which == 0) mult = kk > 0.0 ? 2.0 * inv_n / kk : 0.0;
-    else mult = 0.5 * kk * inv_n;
-    v[rho] = scale(v[rho], (T)mult);
+    const T kk2 = kxx + (T)k2y[j + rho * TT];
+    T mult;
+    if (which == 0) mult = kk2 > (T)0 ? c1 * inv_sqrt(kk2) : (T)0;
+    else mult = c2 * sqrt(kk2);
+    v[rho] = scale(v[rho], mult);
   }
-  pencil_fft<NY, +1>(v, j, mre, mim, lidx, tw);
+  pencil_fft_cx<NY, +1, PL>(v, j, xch, lidx, tw);
   if (active) {
 #pragma unroll
     for (int rho = 0; rho < RMAX; ++rho) base[j + rho * TT] = v[rho];
@@ -571,8 +625,44 @@ static FilmPtrs<T> fptrs(mag_ctx *c) {
   return f;
 }
 
+// Number of row blocks (partial sums per row pass) of the current grid.
+template <typename T>
+static int film_row_blocks(mag_ctx *c) {
+  const FilmGeom G = fgeom(c);
+  int nb = 0;
+  FILM_SWITCH_M(G.nx / 2, { nb = (G.ny + FilmRowShape<MM, T>::P - 1) / FilmRowShape<MM, T>::P; });
+  return nb;
+}
+
+// Regions of d_part used by the passes of one iteration (nb row blocks each).
+struct PartRegions {
+  double *C, *R, *A, *X;
+  int nb;
+};
+
+template <typename T>
+static PartRegions film_regions(mag_ctx *c) {
+  PartRegions r;
+  r.nb = film_row_blocks<T>(c);
+  r.C = c->d_part;
+  r.R = c->d_part + r.nb;
+  r.A = c->d_part + 2 * r.nb;
+  r.X = c->d_part + 3 * r.nb;
+  return r;
+}
+
+static Parts parts(const double *in, int nin, double *out, double *out2 = nullptr, int iter = 0) {
+  Parts p;
+  p.in = in;
+  p.nin = nin;
+  p.out = out;
+  p.out2 = out2;
+  p.iter = iter;
+  return p;
+}
+
 template <typename T, int MODE>
-static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, int kid) {
+static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, int kid) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, kid);
@@ -580,28 +670,29 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, int kid) {
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
-                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->d_part, c->d_it);
+                       c->d_flags, f.S, f.twM, f.twN, G, hde, pp, c->d_it);
   });
   return MAG_OK;
 }
 
 template <typename T, int MODE>
-static int film_inv(mag_ctx *c, T *X, double *xd, double hde, int *nblk_out, int kid) {
+static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, kid);
   FILM_SWITCH_M(G.nx / 2, {
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
-    *nblk_out = nblk;
     hipLaunchKernelGGL((film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
-                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, c->d_part, c->d_it);
+                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it);
   });
   return MAG_OK;
 }
 
+// which = 0: 2/|k|; which = 1: |k|/2.  pp.in != NULL: take the stop decision
+// of evaluation pp.iter from the residual sums pp.in first.
 template <typename T>
-static int film_col(mag_ctx *c, int which) {
+static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, K_FILM_COLS);
@@ -609,24 +700,31 @@ static int film_col(mag_ctx *c, int which) {
     using CS = FilmColShape<NN, T>;
     const int nblk = (G.kx + CS::P - 1) / CS::P;
     hipLaunchKernelGGL((film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x, f.k2y,
-                       1.0 / (double)c->nnode, which, f.twY, c->d_it);
+                       1.0 / (double)c->nnode, which, f.twY, pp, c->d_it, c->h_it);
   });
   return MAG_OK;
 }
 
+// One inner iteration (evaluation i of (11), then the update (12)):
+//   rows_fwd  H: shift A (from the previous update's sums), R2C of H - dh_e
+//   cols      2/|k|
+//   rows_inv  G, sums of G over free space                       -> C
+//   rows_fwd  gdot = G - C (C from those sums), sums of |gdot|    -> r
+//   cols      stop decision on r, then |k|/2
+//   rows_inv  H -= lambda V on free space, sums of H - dh_e       -> A
 template <typename T>
-static int film_iteration(mag_ctx *c, double hde) {
+static int film_iteration(mag_ctx *c, double hde, int i) {
   const FilmPtrs<T> f = fptrs<T>(c);
-  int rc, nblk = 0;
-  if ((rc = film_fwd<T, 0>(c, f.H, nullptr, hde, K_FILM_ROWS_FWD_H))) return rc;
+  const PartRegions pr = film_regions<T>(c);
+  int rc;
+  if ((rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(i == 0 ? nullptr : pr.A, pr.nb, nullptr),
+                           K_FILM_ROWS_FWD_H)))
+    return rc;
   if ((rc = film_col<T>(c, 0))) return rc;
-  if ((rc = film_inv<T, 0>(c, f.G, nullptr, hde, &nblk, K_FILM_ROWS_INV_G))) return rc;
-  if ((rc = run_finalize_mean(c, nblk, 0))) return rc;                 // C
-  if ((rc = film_fwd<T, 1>(c, f.G, nullptr, hde, K_FILM_ROWS_FWD_G))) return rc;
-  if ((rc = run_finalize_stop(c, nblk))) return rc;                    // r, done
-  if ((rc = film_col<T>(c, 1))) return rc;
-  if ((rc = film_inv<T, 1>(c, f.H, nullptr, hde, &nblk, K_FILM_ROWS_INV_UPD))) return rc;
-  return run_finalize_mean(c, nblk, 1);                                // A
+  if ((rc = film_inv<T, 0>(c, f.G, nullptr, hde, parts(nullptr, 0, pr.C), K_FILM_ROWS_INV_G))) return rc;
+  if ((rc = film_fwd<T, 1>(c, f.G, nullptr, hde, parts(pr.C, pr.nb, pr.R), K_FILM_ROWS_FWD_G))) return rc;
+  if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, i)))) return rc;
+  return film_inv<T, 1>(c, f.H, nullptr, hde, parts(nullptr, 0, pr.A), K_FILM_ROWS_INV_UPD);
 }
 
 template <typename T>
@@ -666,7 +764,7 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
     const int k = block < kmax - issued ? block : kmax - issued;
     for (int i = 0; i < k; ++i) {
       c->cur_iter = issued + i;
-      if ((rc = film_iteration<T>(c, hde))) return rc;
+      if ((rc = film_iteration<T>(c, hde, issued + i))) return rc;
     }
     c->cur_iter = -1;
     issued += k;
@@ -716,9 +814,9 @@ static int film_observe_t(mag_ctx *c, const double *state, double t, double *hz,
   if (int rc0 = run_iter_init(c, is)) return rc0;
   int rc, nblk = 0;
   if (hz) {
-    if ((rc = film_fwd<T, 2>(c, nullptr, state, 0.0, K_MISC))) return rc;
+    if ((rc = film_fwd<T, 2>(c, nullptr, state, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
     if ((rc = film_col<T>(c, 1))) return rc;
-    if ((rc = film_inv<T, 2>(c, nullptr, hz, he[2], &nblk, K_MISC))) return rc;
+    if ((rc = film_inv<T, 2>(c, nullptr, hz, he[2], parts(nullptr, 0, nullptr), K_MISC))) return rc;
   }
   ProfScope ps(c, K_MISC);
   if (j) hipLaunchKernelGGL(film_current, dim3(nb), dim3(256), 0, c->stream, state, j, G.nx, G.ny, G.idx, G.idy);
@@ -748,9 +846,9 @@ static int film_hz_transpose_t(mag_ctx *c, const double *hz_bar, double *state_b
   IterState is{};
   if (int rc0 = run_iter_init(c, is)) return rc0;
   int rc, nblk = 0;
-  if ((rc = film_fwd<T, 2>(c, nullptr, hz_bar, 0.0, K_MISC))) return rc;
+  if ((rc = film_fwd<T, 2>(c, nullptr, hz_bar, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
   if ((rc = film_col<T>(c, 1))) return rc;
-  if ((rc = film_inv<T, 2>(c, nullptr, state_bar, 0.0, &nblk, K_MISC))) return rc;
+  if ((rc = film_inv<T, 2>(c, nullptr, state_bar, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
@@ -795,11 +893,11 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
     hipLaunchKernelGGL(sum_blocks, dim3(nb), dim3(256), 0, c->stream, ybar, n, c->d_part);
   }
   if ((rc = run_finalize_mean(c, nb, 1))) return rc;                  // A = sum_D ybar / #out
-  if ((rc = film_fwd<T, 5>(c, nullptr, ybar, 0.0, K_VJP))) return rc;   // ybar - A on free space
+  const PartRegions pr = film_regions<T>(c);
+  if ((rc = film_fwd<T, 5>(c, nullptr, ybar, 0.0, parts(nullptr, 0, nullptr), K_VJP))) return rc;
   if ((rc = film_col<T>(c, 0))) return rc;                             // K1
-  if ((rc = film_inv<T, 5>(c, Mu, nullptr, 0.0, &nblk, K_VJP))) return rc;
-  if ((rc = run_finalize_mean(c, nblk, 0))) return rc;                // C = mean_out mu
-  if ((rc = run_finalize_mean(c, nblk, 2, nblk))) return rc;          // thr = tol mean_D |mu|
+  if ((rc = film_inv<T, 5>(c, Mu, nullptr, 0.0, parts(nullptr, 0, pr.C, pr.X), K_VJP))) return rc;
+  if ((rc = run_finalize_mean(c, pr.nb, 2, (int)(pr.X - c->d_part)))) return rc;   // thr = tol mean_D |mu|
   MAG_HIP(c, hipGetLastError());
   const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
   int issued = 0;
@@ -809,15 +907,15 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
     const int k = block < kmax - issued ? block : kmax - issued;
     for (int i = 0; i < k; ++i) {
       c->cur_iter = issued + i;
-      if ((rc = film_fwd<T, 1>(c, Mu, nullptr, 0.0, K_VJP))) return rc;    // P_out (mu - C), sums |.|
-      if ((rc = run_finalize_stop(c, nblk))) return rc;
-      if ((rc = film_col<T>(c, 1))) return rc;                            // K2
-      if ((rc = film_inv<T, 3>(c, Z, nullptr, 0.0, &nblk, K_VJP))) return rc;
-      if ((rc = run_finalize_mean(c, nblk, 1))) return rc;                // A = sum_D z / #out
-      if ((rc = film_fwd<T, 0>(c, Z, nullptr, 0.0, K_VJP))) return rc;    // z - A on free space
-      if ((rc = film_col<T>(c, 0))) return rc;                            // K1
-      if ((rc = film_inv<T, 4>(c, Mu, nullptr, 0.0, &nblk, K_VJP))) return rc;
-      if ((rc = run_finalize_mean(c, nblk, 0))) return rc;                // C = mean_out mu
+      const int it_i = issued + i;
+      // nu = mu - C (C from the sums of mu), P_out nu, sums of |nu| over free space
+      if ((rc = film_fwd<T, 1>(c, Mu, nullptr, 0.0, parts(pr.C, pr.nb, pr.R), K_VJP))) return rc;
+      if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, it_i)))) return rc;   // stop?, K2
+      if ((rc = film_inv<T, 3>(c, Z, nullptr, 0.0, parts(nullptr, 0, pr.A), K_VJP))) return rc;
+      // z - A on free space (A from the sums of z), K1
+      if ((rc = film_fwd<T, 0>(c, Z, nullptr, 0.0, parts(pr.A, pr.nb, nullptr), K_VJP))) return rc;
+      if ((rc = film_col<T>(c, 0))) return rc;
+      if ((rc = film_inv<T, 4>(c, Mu, nullptr, 0.0, parts(nullptr, 0, pr.C), K_VJP))) return rc;
     }
     c->cur_iter = -1;
     issued += k;

@@ -50,6 +50,30 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return sh[0];
 }
 
+// Sum of part[0..n) in a fixed order that does not depend on the block size
+// (THREADS >= 256): 256 strided partial sums, then a pairwise tree.  Every
+// block of every kernel that calls it on the same data gets the same bits,
+// and so does a one-block finalize kernel that sums the same way.
+template <int THREADS>
+__device__ __forceinline__ double fixed_sum256(const double *__restrict__ part, int n, double *sh) {
+  static_assert(THREADS >= 256, "fixed_sum256 needs at least 256 threads");
+  const int t = threadIdx.x;
+  if (t < 256) {
+    double s = 0.0;
+    for (int i = t; i < n; i += 256) s += part[i];
+    sh[t] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
 // ---------------------------------------------------------------- row helpers
 // After a length-M forward FFT of z[m] = x[2m] + i x[2m+1] (thread j holds
 // Z[j + rho TT] in v), form the half spectrum X[k], k = 0..M, of the real row:

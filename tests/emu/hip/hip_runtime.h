@@ -67,6 +67,8 @@ inline hipError_t hipMalloc(void *p, size_t n) {
 }
 template <typename T>
 inline hipError_t hipMallocAsync(T **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
+inline float rsqrtf(float x) { return 1.0f / std::sqrt(x); }
+#define __align__(n) alignas(n)
 #define hipHostMallocCoherent 0x40000000u
 inline hipError_t hipHostMalloc(void *p, size_t n, unsigned = 0) { return hipMalloc(p, n); }
 inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
