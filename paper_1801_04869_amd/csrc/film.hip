@@ -78,17 +78,23 @@ __device__ __forceinline__ T film_edge_e(const double *__restrict__ g, const uin
 }
 
 // dh_z/dt = -(d_x e_y - d_y e_x) at inside nodes (eq. (9)); free-space nodes
-// keep the warm start (or take dh_e/dt).  Per-block sums of H - dh_e over D.
+// keep the warm start (or take dh_e/dt).  Each thread handles kStencilNpt
+// nodes 256 apart; one partial sum of H - dh_e over D per block.
+constexpr int kStencilNpt = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(256) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
                                                     T *__restrict__ H, FilmGeom G, FilmLaw law, double hde,
                                                     int warm, double *__restrict__ part) {
-  __shared__ double red[256];
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double red[4];
   const long long n = (long long)G.nx * G.ny;
+  const long long i0 = (long long)blockIdx.x * (256 * kStencilNpt) + threadIdx.x;
   double acc = 0.0;
-  if (i < n) {
+#pragma unroll 1
+  for (int k = 0; k < kStencilNpt; ++k) {
+    const long long i = i0 + (long long)k * 256;
+    if (i >= n) break;
     const int p = (int)(i % G.nx), q = (int)(i / G.nx);
     T h;
     if (flags[i] & 1) {
@@ -105,9 +111,9 @@ __global__ void __launch_bounds__(256) film_stencil(const double *__restrict__ g
       h = (T)hde;
       H[i] = h;
     }
-    acc = (double)h - hde;
+    acc += (double)h - hde;
   }
-  const double s = block_sum<256>(acc, red);
+  const double s = block_total<256>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -186,7 +192,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   using PL = typename RS::PL;
   constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
   __shared__ __align__(16) T lds[RS::LDS_T];
-  __shared__ double red[RS::THREADS];
+  __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
@@ -196,9 +202,9 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   // MODE 0: the shift A of (10) from the previous update's sums (or the
   // stencil's, already reduced into it->A); MODE 1: C = free-space mean of G.
   double shift = 0.0;
-  if constexpr (MODE == 0) shift = pp.in ? fixed_sum256<RS::THREADS>(pp.in, pp.nin, red) * it->inv_nout : it->A;
+  if constexpr (MODE == 0) shift = pp.in ? parts_sum(pp.in, pp.nin) * it->inv_nout : it->A;
   if constexpr (MODE == 1) {
-    shift = fixed_sum256<RS::THREADS>(pp.in, pp.nin, red) * it->inv_nout;
+    shift = parts_sum(pp.in, pp.nin) * it->inv_nout;
     if (blockIdx.x == 0 && threadIdx.x == 0) it->C = shift;
   }
   if constexpr (MODE == 5) shift = it->A;
@@ -263,7 +269,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
   }
   if constexpr (MODE == 1) {
-    const double sblk = block_sum<RS::THREADS>(acc, red);
+    const double sblk = block_total<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) pp.out[blk] = sblk;
   }
 }
@@ -287,7 +293,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   using PL = typename RS::PL;
   constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
   __shared__ __align__(16) T lds[RS::LDS_T];
-  __shared__ double red[RS::THREADS];
+  __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
@@ -356,12 +362,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     }
   }
   if constexpr (MODE != 2) {
-    const double sblk = block_sum<RS::THREADS>(acc, red);
+    const double sblk = block_total<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) pp.out[blk] = sblk;
   }
   if constexpr (MODE == 5) {
-    __syncthreads();
-    const double sblk2 = block_sum<RS::THREADS>(acc2, red);
+    const double sblk2 = block_total<RS::THREADS>(acc2, red + RS::THREADS / 64);
     if (threadIdx.x == 0) pp.out2[blk] = sblk2;
   }
 }
@@ -382,8 +387,7 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   if (pp.in) {
     // Stop test of Sec. 2.3 on the residual sums of the previous pass: every
     // block takes the same decision; block 0 records it.
-    __shared__ double red[CS::THREADS];
-    const double r = fixed_sum256<CS::THREADS>(pp.in, pp.nin, red) * it->inv_nout;
+    const double r = parts_sum(pp.in, pp.nin) * it->inv_nout;
     const int iters = pp.iter + 1;
     const int fixed = it->fixed;
     const int done = !isfinite(r) ? 2 : (fixed > 0 ? (iters >= fixed ? 1 : 0) : (r < it->thr ? 1 : 0));
@@ -443,9 +447,9 @@ __global__ void __launch_bounds__(256) film_current(const double *__restrict__ g
 
 __global__ void __launch_bounds__(256) sum_blocks(const double *__restrict__ x, long long n,
                                                   double *__restrict__ part) {
-  __shared__ double red[256];
+  __shared__ double red[4];
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  const double s = block_sum<256>(i < n ? x[i] : 0.0, red);
+  const double s = block_total<256>(i < n ? x[i] : 0.0, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -747,13 +751,13 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   law.jc0 = c->jc0;
   law.has_jc = c->has_jc_map ? 1 : 0;
   const long long n = c->nnode;
-  const int nb = (int)((n + 255) / 256);
+  const int nbs = (int)((n + 256 * kStencilNpt - 1) / (256 * kStencilNpt));   // stencil blocks
   {
     ProfScope ps(c, K_FILM_STENCIL);
-    hipLaunchKernelGGL((film_stencil<T>), dim3(nb), dim3(256), 0, c->stream, state, c->d_mat, c->d_flags,
+    hipLaunchKernelGGL((film_stencil<T>), dim3(nbs), dim3(256), 0, c->stream, state, c->d_mat, c->d_flags,
                        reinterpret_cast<const T *>(c->d_jc), f.H, G, law, hde, c->warm_valid ? 1 : 0, c->d_part);
   }
-  int rc = run_finalize_mean(c, nb, 1);   // A^0
+  int rc = run_finalize_mean(c, nbs, 1);   // A^0
   if (rc) return rc;
   MAG_HIP(c, hipGetLastError());
   const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
@@ -792,7 +796,8 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   c->warm_valid = true;
   {
     ProfScope ps(c, K_MISC);
-    hipLaunchKernelGGL((film_out<T>), dim3(nb), dim3(256), 0, c->stream, f.G, out, n, c->d_it);
+    hipLaunchKernelGGL((film_out<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, f.G, out, n,
+                       c->d_it);
   }
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;

@@ -74,6 +74,41 @@ __device__ __forceinline__ double fixed_sum256(const double *__restrict__ part, 
   return r;
 }
 
+// Sum over the 64 lanes of a wavefront by an xor butterfly: every lane ends
+// with the same bits (each step adds two equal-order partial sums).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Sum of part[0..n) computed by one wavefront in a fixed order (lane l adds
+// part[l], part[l+64], ... then the butterfly): every wavefront of every block
+// that calls it on the same data gets the same bits, with no barrier.
+__device__ __forceinline__ double parts_sum(const double *__restrict__ part, int n) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) s += part[i];
+  return wave_sum(s);
+}
+
+// Block total of one double per thread (fixed order: butterfly per wavefront,
+// then the wavefront sums in order); valid in thread 0.  sh: THREADS / 64
+// doubles.  Contains one barrier.
+template <int THREADS>
+__device__ __forceinline__ double block_total(double v, double *sh) {
+  constexpr int NW = (THREADS + 63) / 64;
+  const double w = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += sh[i];
+  }
+  return s;
+}
+
 // ---------------------------------------------------------------- row helpers
 // After a length-M forward FFT of z[m] = x[2m] + i x[2m+1] (thread j holds
 // Z[j + rho TT] in v), form the half spectrum X[k], k = 0..M, of the real row:

@@ -44,6 +44,23 @@ inline unsigned char *dyn = nullptr;
 
 inline void __syncthreads() { emu::bar->arrive_and_wait(); }
 
+// Cross-lane exchange within a 64-wide wavefront, emulated through a per-block
+// buffer between two block barriers (all work-items of the block must call it
+// together, which the library's uniform reductions do).
+namespace emu {
+inline std::vector<double> *xbuf = nullptr;
+}
+inline double __shfl_xor(double v, int mask, int width = 64) {
+  const unsigned t = threadIdx.x + emu::bDim.x * (threadIdx.y + emu::bDim.y * threadIdx.z);
+  (*emu::xbuf)[t] = v;
+  __syncthreads();
+  const unsigned base = t & ~63u;
+  const double r = (*emu::xbuf)[base + ((t - base) ^ (unsigned)mask)];
+  __syncthreads();
+  (void)width;
+  return r;
+}
+
 using std::exp;
 using std::fabs;
 using std::fmax;
@@ -99,6 +116,8 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t shm, A... args) {
         emu::dyn = d;
         std::barrier<> br((std::ptrdiff_t)nt);
         emu::bar = &br;
+        std::vector<double> xb(((nt + 63) / 64) * 64, 0.0);
+        emu::xbuf = &xb;
         std::vector<std::thread> th;
         th.reserve(nt);
         for (unsigned t = 0; t < nt; ++t)
