@@ -97,6 +97,7 @@ struct mag_ctx {
   void *d_H = nullptr;            // iterate: film dh_z/dt on nodes; bulk dh/dt on edges (precision type)
   void *d_G = nullptr;            // film: G of (11) (precision type)
   void *d_S = nullptr;            // half spectrum, ncomp planes of kx*ny*nz complex
+  void *d_w = nullptr;            // film: K1 and K2 applied to the free-space indicator (precision type)
   void *d_box = nullptr;          // bulk stencil scratch: j then e on the pruning box (precision type)
   long long boxvol = 0;
   int boxn[3] = {0, 0, 0};

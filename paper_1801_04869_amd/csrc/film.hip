@@ -186,7 +186,7 @@ template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
                   cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
-                  FilmGeom G, double hde, Parts pp, IterState *__restrict__ it) {
+                  FilmGeom G, double hde, Parts pp, IterState *__restrict__ it, const T *__restrict__ w1) {
   if (it->done) return;
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
@@ -224,6 +224,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           X[ro + p] = h;
         }
         val[e] = (T)((double)h - hde);
+        if (w1) acc += (double)w1[ro + p] * ((double)h - hde);
       } else if constexpr (MODE == 1) {
         const double gd = (double)X[ro + p] - shift;
         if (!(flags[ro + p] & 1)) {
@@ -271,6 +272,133 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   if constexpr (MODE == 1) {
     const double sblk = block_total<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) pp.out[blk] = sblk;
+  }
+  if constexpr (MODE == 0) {
+    if (pp.out) {
+      const double sblk = block_total<RS::THREADS>(acc, red);
+      if (threadIdx.x == 0) pp.out[blk] = sblk;
+    }
+  }
+}
+
+// Fused row pass of the forward iteration: complex-to-real of the transposed
+// spectrum, a pointwise step, real-to-complex of the result (transposed out).
+// The free-space means C and A are not summed over the field itself: since
+// K1 and K2 are symmetric, sum_out K x = sum_D (K 1_out) x, so with
+// w = K 1_out precomputed they come from dot products taken one pass earlier.
+// MODE 6 (after the 2/|k| pass): G = C2R; write G; C = (sum of w1 (H - dh_e))
+//        / #out; gdot = G - C; sums over free space of |gdot| (out) and of
+//        w2 gdot (out2); R2C of gdot on free space.
+// MODE 7 (after the |k|/2 pass): V = C2R; on free space H <- H - lambda V - A
+//        with A = -lambda (sum of w2 gdot) / #out, the shift that restores
+//        (10) (sum_D (H - dh_e) was 0 before the update); sums of w1 (H - dh_e)
+//        over D (out, the next C); R2C of H - dh_e.
+template <typename T, int M, int MODE>
+__global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
+    film_rows_fused(T *__restrict__ X, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
+                    const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
+                    FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it) {
+  if (it->done) return;
+  using RS = FilmRowShape<M, T>;
+  using PL = typename RS::PL;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ __align__(16) T lds[RS::LDS_T];
+  __shared__ double red[2 * (RS::THREADS / 64)];
+  const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
+  const int q0 = blk * P;
+  const int q = q0 + pr;
+  const bool active = q < G.ny;
+  const long long ro = (long long)(active ? q : 0) * G.nx;
+  cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
+  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
+    const int k = idx / P, r = idx % P;
+    tile[k * SP + r] = q0 + r < G.ny ? S[(long long)k * G.ny + q0 + r] : cx<T>{(T)0, (T)0};
+  }
+  double cst;
+  if constexpr (MODE == 6) {
+    cst = parts_sum(pp.in, pp.nin) * it->inv_nout;   // C
+    if (blockIdx.x == 0 && threadIdx.x == 0) it->C = cst;
+  } else {
+    cst = -lam * parts_sum(pp.in, pp.nin) * it->inv_nout;   // A
+  }
+  __syncthreads();
+  cx<T> v[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    const cx<T> a = tile[k * SP + pr];
+    const cx<T> b = tile[(M - k) * SP + pr];
+    const cx<T> sum = {a.x + b.x, a.y - b.y};
+    const cx<T> dif = {a.x - b.x, a.y + b.y};
+    const cx<T> wd = cmulc(dif, twN[k]);
+    v[rho] = {sum.x - wd.y, sum.y + wd.x};
+  }
+  if constexpr (PL::S == 1) __syncthreads();
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
+  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  double acc = 0.0, acc2 = 0.0;
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    T u[2] = {(T)0, (T)0};
+    const T val[2] = {v[rho].x, v[rho].y};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = 2 * (j + rho * TT) + e;
+      if (!active) continue;
+      const bool out = !(flags[ro + p] & 1);
+      if constexpr (MODE == 6) {
+        X[ro + p] = val[e];
+        if (out) {
+          const double gd = (double)val[e] - cst;
+          acc += fabs(gd);
+          acc2 += (double)w[ro + p] * gd;
+          u[e] = (T)gd;
+        }
+      } else {
+        T h = X[ro + p];
+        if (out) {
+          h = (T)((double)h - lam * (double)val[e] - cst);
+          X[ro + p] = h;
+        }
+        const double d = (double)h - hde;
+        acc += (double)w[ro + p] * d;
+        u[e] = (T)d;
+      }
+    }
+    v[rho] = {u[0], u[1]};
+  }
+  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) xch[j + rho * TT] = v[rho];
+  __syncthreads();
+  cx<T> xk[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    const int km = (M - k) & (M - 1);
+    const cx<T> zk = v[rho];
+    const cx<T> zm = conj(xch[km]);
+    const cx<T> sum = zk + zm, dif = zk - zm;
+    const cx<T> wd = cmul(twN[k], dif);
+    xk[rho] = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
+  }
+  const cx<T> xm = {v[0].x - v[0].y, (T)0};
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
+  if (j == 0) tile[M * SP + pr] = xm;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
+    const int k = idx / P, r = idx % P;
+    if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
+  }
+  const double s1 = block_total<RS::THREADS>(acc, red);
+  if (threadIdx.x == 0) pp.out[blk] = s1;
+  if constexpr (MODE == 6) {
+    const double s2 = block_total<RS::THREADS>(acc2, red + RS::THREADS / 64);
+    if (threadIdx.x == 0) pp.out2[blk] = s2;
   }
 }
 
@@ -612,6 +740,7 @@ struct FilmPtrs {
   cx<T> *S;
   const cx<T> *twM, *twY, *twN;
   const double *k2x, *k2y;
+  T *w1, *w2;   // K1 1_out and K2 1_out
 };
 
 template <typename T>
@@ -626,6 +755,8 @@ static FilmPtrs<T> fptrs(mag_ctx *c) {
   f.twN = tw + c->tw_off[3];
   f.k2x = c->d_sym + c->sym_off[0];
   f.k2y = c->d_sym + c->sym_off[1];
+  f.w1 = reinterpret_cast<T *>(c->d_w);
+  f.w2 = f.w1 ? f.w1 + c->nnode : nullptr;
   return f;
 }
 
@@ -674,7 +805,8 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, in
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
-                       c->d_flags, f.S, f.twM, f.twN, G, hde, pp, c->d_it);
+                       c->d_flags, f.S, f.twM, f.twN, G, hde, pp, c->d_it,
+                       (MODE == 0 && pp.out) ? (const T *)f.w1 : (const T *)nullptr);
   });
   return MAG_OK;
 }
@@ -689,6 +821,20 @@ static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid)
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
                        c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it);
+  });
+  return MAG_OK;
+}
+
+template <typename T, int MODE>
+static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int kid) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  ProfScope ps(c, kid);
+  FILM_SWITCH_M(G.nx / 2, {
+    using RS = FilmRowShape<MM, T>;
+    const int nblk = (G.ny + RS::P - 1) / RS::P;
+    hipLaunchKernelGGL((film_rows_fused<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
+                       f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it);
   });
   return MAG_OK;
 }
@@ -709,26 +855,27 @@ static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)
   return MAG_OK;
 }
 
-// One inner iteration (evaluation i of (11), then the update (12)):
-//   rows_fwd  H: shift A (from the previous update's sums), R2C of H - dh_e
-//   cols      2/|k|
-//   rows_inv  G, sums of G over free space                       -> C
-//   rows_fwd  gdot = G - C (C from those sums), sums of |gdot|    -> r
-//   cols      stop decision on r, then |k|/2
-//   rows_inv  H -= lambda V on free space, sums of H - dh_e       -> A
+// One inner iteration i (evaluation i of (11), then the update (12)), four
+// passes over the spectrum:
+//   (i = 0: rows_fwd  H: shift A^0, R2C of H - dh_e, sums of w1 (H - dh_e))
+//   cols       2/|k|
+//   fused 6    G, C from the w1 sums, gdot = G - C, sums of |gdot| and of
+//              w2 gdot over free space, R2C of gdot on free space
+//   cols       stop decision on the |gdot| sums, then |k|/2
+//   fused 7    H <- H - lambda V - A on free space (A from the w2 sums),
+//              sums of w1 (H - dh_e), R2C of H - dh_e (next iteration)
 template <typename T>
 static int film_iteration(mag_ctx *c, double hde, int i) {
   const FilmPtrs<T> f = fptrs<T>(c);
   const PartRegions pr = film_regions<T>(c);
   int rc;
-  if ((rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(i == 0 ? nullptr : pr.A, pr.nb, nullptr),
-                           K_FILM_ROWS_FWD_H)))
+  if (i == 0 &&
+      (rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(nullptr, 0, pr.C), K_FILM_ROWS_FWD_H)))
     return rc;
   if ((rc = film_col<T>(c, 0))) return rc;
-  if ((rc = film_inv<T, 0>(c, f.G, nullptr, hde, parts(nullptr, 0, pr.C), K_FILM_ROWS_INV_G))) return rc;
-  if ((rc = film_fwd<T, 1>(c, f.G, nullptr, hde, parts(pr.C, pr.nb, pr.R), K_FILM_ROWS_FWD_G))) return rc;
+  if ((rc = film_fused<T, 6>(c, f.G, f.w2, hde, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G))) return rc;
   if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, i)))) return rc;
-  return film_inv<T, 1>(c, f.H, nullptr, hde, parts(nullptr, 0, pr.A), K_FILM_ROWS_INV_UPD);
+  return film_fused<T, 7>(c, f.H, f.w1, hde, parts(pr.A, pr.nb, pr.C), K_FILM_ROWS_INV_UPD);
 }
 
 template <typename T>
@@ -973,6 +1120,7 @@ int film_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_mat, n));
   c->npart = (int)((n + 255) / 256 + c->n[1] + 16);   // stencil blocks or one row block per row
   MAG_HIP(c, hipMalloc(&c->d_part, (size_t)c->npart * sizeof(double)));
+  MAG_HIP(c, hipMalloc(&c->d_w, 2 * n * ts));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
   MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
   // |k|^2 per axis: k = 2 pi fftfreq(n, d)
@@ -990,6 +1138,35 @@ int film_alloc(mag_ctx *c) {
   }
   MAG_HIP(c, hipMalloc(&c->d_sym, sym.size() * sizeof(double)));
   MAG_HIP(c, hipMemcpy(c->d_sym, sym.data(), sym.size() * sizeof(double), hipMemcpyHostToDevice));
+  return MAG_OK;
+}
+
+namespace {
+template <typename T>
+__global__ void __launch_bounds__(256) from_double_k(const double *__restrict__ src, T *__restrict__ dst,
+                                                     long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = (T)src[i];
+}
+}  // namespace
+
+// tmp: device double[2n], the indicator in the first half.
+template <typename T>
+static int film_weights_t(mag_ctx *c, double *tmp) {
+  const long long n = c->nnode;
+  T *w = reinterpret_cast<T *>(c->d_w);
+  IterState is{};
+  int rc;
+  if ((rc = run_iter_init(c, is))) return rc;
+  for (int which = 0; which < 2; ++which) {
+    if ((rc = film_fwd<T, 2>(c, nullptr, tmp, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
+    if ((rc = film_col<T>(c, which))) return rc;
+    if ((rc = film_inv<T, 2>(c, nullptr, tmp + n, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
+    ProfScope ps(c, K_MISC);
+    hipLaunchKernelGGL((from_double_k<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, tmp + n,
+                       w + which * n, n);
+  }
+  MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
 
@@ -1016,6 +1193,21 @@ int film_domain(mag_ctx *c) {
   MAG_HIP(c, hipMemcpy(c->d_flags, fl.data(), n, hipMemcpyHostToDevice));
   MAG_HIP(c, hipMemcpy(c->d_mat, m.data(), n, hipMemcpyHostToDevice));
   c->warm_valid = false;
+  // w1 = K1 1_out and w2 = K2 1_out (free-space indicator through the two
+  // Fourier multipliers), used to take the free-space means of the iteration
+  // as dot products.
+  std::vector<double> ind(n);
+  for (long long i = 0; i < n; ++i) ind[i] = fl[i] ? 0.0 : 1.0;
+  double *tmp = nullptr;
+  MAG_HIP(c, hipMalloc(&tmp, 2 * n * sizeof(double)));
+  MAG_HIP(c, hipMemcpy(tmp, ind.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  const int rc = c->prec == MAG_FP64 ? film_weights_t<double>(c, tmp) : film_weights_t<float>(c, tmp);
+  if (rc) {
+    (void)hipFree(tmp);
+    return rc;
+  }
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  MAG_HIP(c, hipFree(tmp));
   return MAG_OK;
 }
 
