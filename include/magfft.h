@@ -126,8 +126,17 @@ int mag_set_field(mag_ctx *ctx, int kind, const double dir[3], double amp, doubl
  * n_inner (host, nullable): number of inner iterations used.
  * The free-space part of the previous call's result is the first guess
  * (warm start, Sec. 2.2); it is dropped after MAG_NOT_CONVERGED.
- * Returns MAG_OK, MAG_NOT_CONVERGED (out undefined) or an error. */
+ * Returns MAG_OK, MAG_NOT_CONVERGED (out undefined) or an error.
+ * With a fixed iteration count (mag_set_solver fixed_iters > 0, film) and
+ * n_inner == NULL the call only enqueues the work and returns MAG_OK at once;
+ * mag_rhs_status then waits and reports a non-finite result. */
 int mag_rhs(mag_ctx *ctx, const double *state, double t, double *out, int *n_inner);
+
+/* Wait for the context's stream; report MAG_E_NUMERIC if the last
+ * asynchronous mag_rhs produced a non-finite residual (and drop the warm
+ * start), MAG_OK otherwise.  n_inner (host, nullable): inner iterations of the
+ * last right-hand side. */
+int mag_rhs_status(mag_ctx *ctx, int *n_inner);
 
 /* One adaptive Bogacki-Shampine 3(2) step attempt (the pair of Matlab's
  * ode23 used in Sec. 2.2) from (state, *t) with step *dt.

@@ -26,6 +26,7 @@ SIGNATURES = {
     "mag_set_solver": (c_int, [c_void_p, c_double, c_double, c_int, c_int]),
     "mag_set_field": (c_int, [c_void_p, c_int, P_double, c_double, c_double, c_double]),
     "mag_rhs": (c_int, [c_void_p, c_void_p, c_double, c_void_p, P_int]),
+    "mag_rhs_status": (c_int, [c_void_p, P_int]),
     "mag_step": (c_int, [c_void_p, c_void_p, P_double, P_double, c_double, c_double, P_int]),
     "mag_integrate": (c_int, [c_void_p, c_void_p, c_double, c_double, c_double, c_double, P_double, c_int, P_int]),
     "mag_observe": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, P_double]),

@@ -90,12 +90,20 @@ class Context:
         self._check(self._L.mag_set_field(self._h, kind, d, amp, omega, rate))
 
     # ---------------------------------------------------------- evaluation
-    def rhs(self, state, t, out):
-        """out = f(state, t); returns (status, n_inner); status OK or NOT_CONVERGED."""
+    def rhs(self, state, t, out, wait=True):
+        """out = f(state, t); returns (status, n_inner); status OK or NOT_CONVERGED.
+        wait=False with a fixed iteration count: enqueue only (n_inner None);
+        rhs_status() reports the outcome."""
         it = ctypes.c_int(0)
         rc = self._L.mag_rhs(self._h, _ptr(state, torch.float64), float(t), _ptr(out, torch.float64),
-                             ctypes.byref(it))
+                             ctypes.byref(it) if wait else None)
         self._check(rc, allow=(OK, NOT_CONVERGED))
+        return rc, (it.value if wait else None)
+
+    def rhs_status(self):
+        it = ctypes.c_int(0)
+        rc = self._L.mag_rhs_status(self._h, ctypes.byref(it))
+        self._check(rc)
         return rc, it.value
 
     def step(self, state, t, dt, rtol=1e-3, atol=1e-6):

@@ -561,7 +561,23 @@ int mag_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner
   if (state == out) return set_error(c, MAG_E_ARG, "out must not alias state");
   if (!std::isfinite(t)) return set_error(c, MAG_E_ARG, "t is not finite");
   c->fsal_valid = false;
-  return rhs_impl(c, state, t, out, n_inner);
+  c->rhs_async = n_inner == nullptr && c->fixed_iters > 0 && c->dim == 2;
+  rc = rhs_impl(c, state, t, out, n_inner);
+  c->rhs_async = false;
+  return rc;
+}
+
+int mag_rhs_status(mag_ctx *c, int *n_inner) {
+  CHECK_CTX(c);
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  if (n_inner) *n_inner = c->h_it->iters;
+  if (!c->async_pending) return MAG_OK;
+  c->async_pending = false;
+  if (c->h_it->done == 2 || !std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C)) {
+    c->warm_valid = false;
+    return set_error(c, MAG_E_NUMERIC, "non-finite residual");
+  }
+  return MAG_OK;
 }
 
 int mag_reset_warm_start(mag_ctx *c) {

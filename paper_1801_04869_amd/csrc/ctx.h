@@ -128,6 +128,8 @@ struct mag_ctx {
   // instrumentation
   bool debug_sync = false;        // MAG_DEBUG_SYNC=1: synchronise and check after every launch
   bool warm_enabled = true;   // start each RHS from the previous free-space solution
+  bool rhs_async = false;      // the current mag_rhs returns without waiting (fixed count, no n_inner)
+  bool async_pending = false;  // an asynchronous mag_rhs has not been checked yet
   bool prof_on = false;
   int prof_only = -1;   // record only this kernel id (-1: all)
   std::vector<mag::ProfRec> prof;

@@ -919,7 +919,22 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
     }
     c->cur_iter = -1;
     issued += k;
+    // out = G - C, enqueued before the poll: right whenever this block ends
+    // the iteration (it is enqueued again after a further block otherwise)
+    {
+      ProfScope ps(c, K_MISC);
+      hipLaunchKernelGGL((film_out<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, f.G, out, n,
+                         c->d_it);
+    }
     MAG_HIP(c, hipGetLastError());
+    if (c->rhs_async && issued >= kmax) {
+      // fixed count, no host scalar wanted: return without waiting; the
+      // status is checked by mag_rhs_status
+      c->async_pending = true;
+      c->last_iters = kmax;
+      c->warm_valid = true;
+      return MAG_OK;
+    }
     MAG_HIP(c, hipStreamSynchronize(c->stream));
     if (c->h_it->done) {
       done = true;
@@ -941,12 +956,6 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   }
   c->last_iters = used;
   c->warm_valid = true;
-  {
-    ProfScope ps(c, K_MISC);
-    hipLaunchKernelGGL((film_out<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, f.G, out, n,
-                       c->d_it);
-  }
-  MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
 

@@ -384,3 +384,27 @@ def test_film_2048_workload_matches_oracle(mask, prec):
     print("film-2048-%s prec %d: rel-L2 %.3e" % (mask, prec, err), flush=True)
     assert st == 0 and rst == 0 and it == rit == 4
     assert err < TOL[prec]
+
+
+def test_film_async_fixed_count_matches_synchronous():
+    """mag_rhs with a fixed count and no n_inner only enqueues; the result and
+    the status reported by mag_rhs_status equal the synchronous call's."""
+    case = film_case(128, 64, L=(2.0, 1.0), kind="offrect", jc_s=0.2)
+    ctx = make_gpu(case, api.FP64, fixed=3)
+    s = torch.from_numpy(case["state"]).cuda()
+    o1, o2 = torch.empty_like(s), torch.empty_like(s)
+    ctx.reset_warm_start()
+    st, it = ctx.rhs(s, 0.1, o1)
+    ctx.reset_warm_start()
+    st2, it2 = ctx.rhs(s, 0.1, o2, wait=False)
+    assert st2 == 0 and it2 is None
+    st3, it3 = ctx.rhs_status()
+    assert st3 == 0 and it3 == it == 3
+    assert torch.equal(o1, o2)
+    bad = case["state"].copy()
+    q, p = np.argwhere(make_oracle(case).in_node)[0]
+    bad[q, p] = np.nan
+    ctx.rhs(torch.from_numpy(bad).cuda(), 0.1, o2, wait=False)
+    with pytest.raises(api.MagError) as e:
+        ctx.rhs_status()
+    assert e.value.code == api.E_NUMERIC
