@@ -232,7 +232,9 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           val[e] = (T)gd;
         }
       } else if constexpr (MODE == 5) {
-        val[e] = (T)(xd[ro + p] - ((flags[ro + p] & 1) ? 0.0 : shift));
+        const double y = xd[ro + p] - ((flags[ro + p] & 1) ? 0.0 : shift);
+        val[e] = (T)y;
+        if (w1) acc += (double)w1[ro + p] * y;
       } else {
         val[e] = (T)xd[ro + p];
       }
@@ -273,10 +275,141 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     const double sblk = block_total<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) pp.out[blk] = sblk;
   }
-  if constexpr (MODE == 0) {
+  if constexpr (MODE == 0 || MODE == 5) {
     if (pp.out) {
       const double sblk = block_total<RS::THREADS>(acc, red);
       if (threadIdx.x == 0) pp.out[blk] = sblk;
+    }
+  }
+}
+
+// Partial sums of the fused transposed iteration: the free-space mean of the
+// new iterate is c_new * (sum of in_new); that of the previous one c_old *
+// (sum of in_old) (in_old == NULL: the first pass, which has no previous one).
+struct AdjParts {
+  const double *in_new, *in_old, *in_a;
+  int nin;
+  double c_new, c_old;
+  double *out, *out2, *out3;
+};
+
+// Fused row passes of the transposed iteration (the adjoint of (10)-(12)):
+// MODE 8: mu_new = C2R (first pass) or mu - C_old - lambda C2R; write mu_new;
+//         nu = mu_new - C_new; sums over free space of |nu| (out) and of
+//         w2 nu (out2), and on the first pass sums of |mu_new| over D (out3);
+//         R2C of nu on free space.
+// MODE 9: z = C2R on free space (0 on the film), zz = z - A_z on free space
+//         with A_z = (sum of w2 nu) / #out (in_a); sums of w1 zz over D (out,
+//         the next mean); R2C of zz.
+template <typename T, int M, int MODE>
+__global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
+    film_rows_adj(T *__restrict__ X, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
+                  const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
+                  FilmGeom G, double lam, AdjParts pp, IterState *__restrict__ it) {
+  if (it->done) return;
+  using RS = FilmRowShape<M, T>;
+  using PL = typename RS::PL;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ __align__(16) T lds[RS::LDS_T];
+  __shared__ double red[3 * (RS::THREADS / 64)];
+  const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
+  const int q0 = blk * P;
+  const int q = q0 + pr;
+  const bool active = q < G.ny;
+  const long long ro = (long long)(active ? q : 0) * G.nx;
+  cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
+  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
+    const int k = idx / P, r = idx % P;
+    tile[k * SP + r] = q0 + r < G.ny ? S[(long long)k * G.ny + q0 + r] : cx<T>{(T)0, (T)0};
+  }
+  double c_new = 0.0, c_old = 0.0, a_z = 0.0;
+  if constexpr (MODE == 8) {
+    c_new = pp.c_new * parts_sum(pp.in_new, pp.nin);
+    if (pp.in_old) c_old = pp.c_old * parts_sum(pp.in_old, pp.nin);
+    if (blockIdx.x == 0 && threadIdx.x == 0) it->C = c_new;
+  } else {
+    a_z = parts_sum(pp.in_a, pp.nin) * it->inv_nout;
+  }
+  __syncthreads();
+  cx<T> v[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    const cx<T> a = tile[k * SP + pr];
+    const cx<T> b = tile[(M - k) * SP + pr];
+    const cx<T> sum = {a.x + b.x, a.y - b.y};
+    const cx<T> dif = {a.x - b.x, a.y + b.y};
+    const cx<T> wd = cmulc(dif, twN[k]);
+    v[rho] = {sum.x - wd.y, sum.y + wd.x};
+  }
+  if constexpr (PL::S == 1) __syncthreads();
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
+  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  double acc = 0.0, acc2 = 0.0, acc3 = 0.0;
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    T u[2] = {(T)0, (T)0};
+    const T val[2] = {v[rho].x, v[rho].y};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = 2 * (j + rho * TT) + e;
+      if (!active) continue;
+      const bool out = !(flags[ro + p] & 1);
+      if constexpr (MODE == 8) {
+        const double mu = pp.in_old ? (double)X[ro + p] - c_old - lam * (double)val[e] : (double)val[e];
+        const T mut = (T)mu;
+        X[ro + p] = mut;
+        acc3 += fabs((double)mut);
+        if (out) {
+          const double nu = (double)mut - c_new;
+          acc += fabs(nu);
+          acc2 += (double)w[ro + p] * nu;
+          u[e] = (T)nu;
+        }
+      } else {
+        const double zz = out ? (double)val[e] - a_z : 0.0;
+        acc += (double)w[ro + p] * zz;
+        u[e] = (T)zz;
+      }
+    }
+    v[rho] = {u[0], u[1]};
+  }
+  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) xch[j + rho * TT] = v[rho];
+  __syncthreads();
+  cx<T> xk[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    const int km = (M - k) & (M - 1);
+    const cx<T> zk = v[rho];
+    const cx<T> zm = conj(xch[km]);
+    const cx<T> sum = zk + zm, dif = zk - zm;
+    const cx<T> wd = cmul(twN[k], dif);
+    xk[rho] = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
+  }
+  const cx<T> xm = {v[0].x - v[0].y, (T)0};
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
+  if (j == 0) tile[M * SP + pr] = xm;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
+    const int k = idx / P, r = idx % P;
+    if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
+  }
+  constexpr int NW = RS::THREADS / 64;
+  const double s1 = block_total<RS::THREADS>(acc, red);
+  if (threadIdx.x == 0) pp.out[blk] = s1;
+  if constexpr (MODE == 8) {
+    const double s2 = block_total<RS::THREADS>(acc2, red + NW);
+    if (threadIdx.x == 0) pp.out2[blk] = s2;
+    if (pp.out3) {
+      const double s3 = block_total<RS::THREADS>(acc3, red + 2 * NW);
+      if (threadIdx.x == 0) pp.out3[blk] = s3;
     }
   }
 }
@@ -636,13 +769,15 @@ __device__ __forceinline__ void film_edge_vjp(const double *__restrict__ g, cons
   }
 }
 
-// Per node (p, q): the edge terms of its x-edge and y-edge, written to
-// E[0..5] planes: own_x, oth_x, jc_x, own_y, oth_y, jc_y.
+// Per node (p, q): the edge terms of its x-edge and y-edge, written to the
+// planes E[0..3] (own_x, oth_x, own_y, oth_y) and, when the jc map is wanted,
+// E[4..5] (jc_x, jc_y); stored in the compute precision.
 template <typename T>
 __global__ void __launch_bounds__(256) film_vjp_edges(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                       const uint8_t *__restrict__ flags, const T *__restrict__ jc,
                                                       const T *__restrict__ mu, FilmGeom G, FilmLaw law,
-                                                      double *__restrict__ E, const IterState *__restrict__ it) {
+                                                      T *__restrict__ E, int want_jc,
+                                                      const IterState *__restrict__ it) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long n = (long long)G.nx * G.ny;
   if (i >= n) return;
@@ -658,41 +793,44 @@ __global__ void __launch_bounds__(256) film_vjp_edges(const double *__restrict__
   const double eby = (hb(p + 1, q) - h0) * G.idx;
   double o, b, cj;
   film_edge_vjp<T>(g, mat, jc, G, law, p, q, 0, ebx, &o, &b, &cj);
-  E[i] = o;
-  E[i + n] = b;
-  E[i + 2 * n] = cj;
+  E[i] = (T)o;
+  E[i + n] = (T)b;
+  if (want_jc) E[i + 4 * n] = (T)cj;
   film_edge_vjp<T>(g, mat, jc, G, law, p, q, 1, eby, &o, &b, &cj);
-  E[i + 3 * n] = o;
-  E[i + 4 * n] = b;
-  E[i + 5 * n] = cj;
+  E[i + 2 * n] = (T)o;
+  E[i + 3 * n] = (T)b;
+  if (want_jc) E[i + 5 * n] = (T)cj;
 }
 
 // Per node: the edge-current cotangents (own part plus a quarter of the
 // neighbour-mean parts of the four other-orientation edges that average this
 // edge into their |j|), then g_bar by the transpose of eq. (2), and the cell
 // jc_bar from its four edges (edge jc = mean of two cells).
-__global__ void __launch_bounds__(256) film_vjp_gather(const double *__restrict__ E, double *__restrict__ gbar,
+template <typename T>
+__global__ void __launch_bounds__(256) film_vjp_gather(const T *__restrict__ E, double *__restrict__ gbar,
                                                        double *__restrict__ jcbar, double jc0, FilmGeom G) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long n = (long long)G.nx * G.ny;
   if (i >= n) return;
   const int p = (int)(i % G.nx), q = (int)(i / G.nx);
   auto at = [&](int pp, int qq) { return (long long)wrap(qq, G.ny) * G.nx + wrap(pp, G.nx); };
-  const double *own_x = E, *oth_x = E + n, *jcx = E + 2 * n, *own_y = E + 3 * n, *oth_y = E + 4 * n,
-               *jcy = E + 5 * n;
+  const T *own_x = E, *oth_x = E + n, *own_y = E + 2 * n, *oth_y = E + 3 * n;
   // x-edge (pp, qq) is averaged into the y-edges (pp, qq), (pp, qq+1), (pp-1, qq), (pp-1, qq+1)
   auto jbx = [&](int pp, int qq) {
-    return own_x[at(pp, qq)] + 0.25 * (oth_y[at(pp, qq)] + oth_y[at(pp, qq + 1)] + oth_y[at(pp - 1, qq)] +
-                                       oth_y[at(pp - 1, qq + 1)]);
+    return (double)own_x[at(pp, qq)] + 0.25 * ((double)oth_y[at(pp, qq)] + (double)oth_y[at(pp, qq + 1)] +
+                                               (double)oth_y[at(pp - 1, qq)] + (double)oth_y[at(pp - 1, qq + 1)]);
   };
   // y-edge (pp, qq) is averaged into the x-edges (pp, qq), (pp+1, qq), (pp, qq-1), (pp+1, qq-1)
   auto jby = [&](int pp, int qq) {
-    return own_y[at(pp, qq)] + 0.25 * (oth_x[at(pp, qq)] + oth_x[at(pp + 1, qq)] + oth_x[at(pp, qq - 1)] +
-                                       oth_x[at(pp + 1, qq - 1)]);
+    return (double)own_y[at(pp, qq)] + 0.25 * ((double)oth_x[at(pp, qq)] + (double)oth_x[at(pp + 1, qq)] +
+                                               (double)oth_x[at(pp, qq - 1)] + (double)oth_x[at(pp + 1, qq - 1)]);
   };
   // j_x(p,q) = (g(p,q+1) - g(p,q))/dy,  j_y(p,q) = -(g(p+1,q) - g(p,q))/dx
   gbar[i] = (jbx(p, q - 1) - jbx(p, q)) * G.idy + (jby(p, q) - jby(p - 1, q)) * G.idx;
-  if (jcbar) jcbar[i] = jc0 * 0.5 * (jcx[i] + jcx[at(p + 1, q)] + jcy[i] + jcy[at(p, q + 1)]);
+  if (jcbar) {
+    const T *jcx = E + 4 * n, *jcy = E + 5 * n;
+    jcbar[i] = jc0 * 0.5 * ((double)jcx[i] + (double)jcx[at(p + 1, q)] + (double)jcy[i] + (double)jcy[at(p, q + 1)]);
+  }
 }
 
 }  // namespace
@@ -806,7 +944,7 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, in
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
                        c->d_flags, f.S, f.twM, f.twN, G, hde, pp, c->d_it,
-                       (MODE == 0 && pp.out) ? (const T *)f.w1 : (const T *)nullptr);
+                       ((MODE == 0 || MODE == 5) && pp.out) ? (const T *)f.w1 : (const T *)nullptr);
   });
   return MAG_OK;
 }
@@ -835,6 +973,20 @@ static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int ki
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_fused<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
                        f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it);
+  });
+  return MAG_OK;
+}
+
+template <typename T, int MODE>
+static int film_adj(mag_ctx *c, T *X, const T *w, AdjParts pp) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  ProfScope ps(c, K_VJP);
+  FILM_SWITCH_M(G.nx / 2, {
+    using RS = FilmRowShape<MM, T>;
+    const int nblk = (G.ny + RS::P - 1) / RS::P;
+    hipLaunchKernelGGL((film_rows_adj<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
+                       f.S, w, f.twM, f.twN, G, c->lambda, pp, c->d_it);
   });
   return MAG_OK;
 }
@@ -1031,8 +1183,7 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   const FilmPtrs<T> f = fptrs<T>(c);
   const long long n = c->nnode;
   const int nb = (int)((n + 255) / 256);
-  const size_t ts = sizeof(T);
-  const long long need = n * (long long)ts + 6 * n * (long long)sizeof(double);
+  const long long need = 6 * n * (long long)sizeof(T);
   if (c->adj_bytes < need) {
     if (c->d_adj) (void)hipFree(c->d_adj);
     c->d_adj = nullptr;
@@ -1040,25 +1191,32 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
     MAG_HIP(c, hipMalloc(&c->d_adj, need));
     c->adj_bytes = need;
   }
-  double *E = reinterpret_cast<double *>(c->d_adj);
-  T *Z = reinterpret_cast<T *>(E + 6 * n);
+  T *E = reinterpret_cast<T *>(c->d_adj);
   T *Mu = f.G;   // the forward's G is scratch between calls
   IterState is{};
   is.fixed = c->fixed_iters;
   is.inv_nout = c->nout > 0 ? 1.0 / (double)c->nout : 0.0;
   is.sum0 = c->tol / (double)n;
-  int rc, nblk = 0;
+  int rc;
   if ((rc = run_iter_init(c, is))) return rc;
   {
     ProfScope ps(c, K_VJP);
     hipLaunchKernelGGL(sum_blocks, dim3(nb), dim3(256), 0, c->stream, ybar, n, c->d_part);
   }
   if ((rc = run_finalize_mean(c, nb, 1))) return rc;                  // A = sum_D ybar / #out
-  const PartRegions pr = film_regions<T>(c);
-  if ((rc = film_fwd<T, 5>(c, nullptr, ybar, 0.0, parts(nullptr, 0, nullptr), K_VJP))) return rc;
-  if ((rc = film_col<T>(c, 0))) return rc;                             // K1
-  if ((rc = film_inv<T, 5>(c, Mu, nullptr, 0.0, parts(nullptr, 0, pr.C, pr.X), K_VJP))) return rc;
-  if ((rc = run_finalize_mean(c, pr.nb, 2, (int)(pr.X - c->d_part)))) return rc;   // thr = tol mean_D |mu|
+  // regions of d_part: residual, w2 sums, w1 sums (two, alternating), scale
+  const int pnb = film_row_blocks<T>(c);
+  double *Rr = c->d_part, *Rw2 = c->d_part + pnb, *Rw1[2] = {c->d_part + 2 * pnb, c->d_part + 3 * pnb},
+         *Rsc = c->d_part + 4 * pnb;
+  const double inv_nout = is.inv_nout, lam = c->lambda;
+  // mu0 = K1 (ybar - A on free space); C0 = <w1, ybar - A 1_out> / #out
+  if ((rc = film_fwd<T, 5>(c, nullptr, ybar, 0.0, parts(nullptr, 0, Rw1[0]), K_VJP))) return rc;
+  if ((rc = film_col<T>(c, 0))) return rc;
+  {
+    AdjParts ap{Rw1[0], nullptr, nullptr, pnb, inv_nout, 0.0, Rr, Rw2, Rsc};
+    if ((rc = film_adj<T, 8>(c, Mu, f.w2, ap))) return rc;
+  }
+  if ((rc = run_finalize_mean(c, pnb, 2, (int)(Rsc - c->d_part)))) return rc;   // thr = tol mean_D |mu0|
   MAG_HIP(c, hipGetLastError());
   const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
   int issued = 0;
@@ -1067,16 +1225,20 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   while (issued < kmax) {
     const int k = block < kmax - issued ? block : kmax - issued;
     for (int i = 0; i < k; ++i) {
-      c->cur_iter = issued + i;
-      const int it_i = issued + i;
-      // nu = mu - C (C from the sums of mu), P_out nu, sums of |nu| over free space
-      if ((rc = film_fwd<T, 1>(c, Mu, nullptr, 0.0, parts(pr.C, pr.nb, pr.R), K_VJP))) return rc;
-      if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, it_i)))) return rc;   // stop?, K2
-      if ((rc = film_inv<T, 3>(c, Z, nullptr, 0.0, parts(nullptr, 0, pr.A), K_VJP))) return rc;
-      // z - A on free space (A from the sums of z), K1
-      if ((rc = film_fwd<T, 0>(c, Z, nullptr, 0.0, parts(pr.A, pr.nb, nullptr), K_VJP))) return rc;
-      if ((rc = film_col<T>(c, 0))) return rc;
-      if ((rc = film_inv<T, 4>(c, Mu, nullptr, 0.0, parts(nullptr, 0, pr.C), K_VJP))) return rc;
+      const int ii = issued + i;
+      c->cur_iter = ii;
+      // stop test on |nu|, then |k|/2 of P_out nu
+      if ((rc = film_col<T>(c, 1, parts(Rr, pnb, nullptr, nullptr, ii)))) return rc;
+      {
+        AdjParts ap{nullptr, nullptr, Rw2, pnb, 0.0, 0.0, Rw1[(ii + 1) & 1], nullptr, nullptr};
+        if ((rc = film_adj<T, 9>(c, nullptr, f.w1, ap))) return rc;   // z, z - A_z, R2C
+      }
+      if ((rc = film_col<T>(c, 0))) return rc;                            // 2/|k|
+      {
+        AdjParts ap{Rw1[(ii + 1) & 1], Rw1[ii & 1], nullptr, pnb, -lam * inv_nout,
+                    ii == 0 ? inv_nout : -lam * inv_nout, Rr, Rw2, nullptr};
+        if ((rc = film_adj<T, 8>(c, Mu, f.w2, ap))) return rc;
+      }
     }
     c->cur_iter = -1;
     issued += k;
@@ -1105,8 +1267,8 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   {
     ProfScope ps(c, K_VJP);
     hipLaunchKernelGGL((film_vjp_edges<T>), dim3(nb), dim3(256), 0, c->stream, state, c->d_mat, c->d_flags,
-                       reinterpret_cast<const T *>(c->d_jc), Mu, G, law, E, c->d_it);
-    hipLaunchKernelGGL(film_vjp_gather, dim3(nb), dim3(256), 0, c->stream, E, gbar, jcbar, c->jc0, G);
+                       reinterpret_cast<const T *>(c->d_jc), Mu, G, law, E, jcbar ? 1 : 0, c->d_it);
+    hipLaunchKernelGGL((film_vjp_gather<T>), dim3(nb), dim3(256), 0, c->stream, E, gbar, jcbar, c->jc0, G);
   }
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
@@ -1127,7 +1289,7 @@ int film_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_S, c->nspec * 2 * ts));
   MAG_HIP(c, hipMalloc(&c->d_flags, n));
   MAG_HIP(c, hipMalloc(&c->d_mat, n));
-  c->npart = (int)((n + 255) / 256 + c->n[1] + 16);   // stencil blocks or one row block per row
+  c->npart = (int)((n + 255) / 256 + 2 * c->n[1] + 16);   // 256-node blocks, or up to 5 regions of row blocks
   MAG_HIP(c, hipMalloc(&c->d_part, (size_t)c->npart * sizeof(double)));
   MAG_HIP(c, hipMalloc(&c->d_w, 2 * n * ts));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
