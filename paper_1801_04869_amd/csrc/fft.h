@@ -230,12 +230,69 @@ __device__ __forceinline__ void twiddle_powers(cx<T> w, cx<T>* wp) {
   });
 }
 
+// Offset of stage s's twiddles in a thread's preloaded set (stages 1..S-1,
+// RMAX / R[s] entries each).
+template <typename PL>
+constexpr int plan_twoff(int s) {
+  int o = 0;
+  for (int i = 1; i < s; ++i) o += PL::RMAX / PL::R[i];
+  return o;
+}
+
+// The inter-stage twiddle entries one thread of a pencil transform reads,
+// loaded once into registers (they depend only on the thread's index j, and
+// the inverse transform uses the same entries conjugated).  Issuing these
+// loads with the data loads takes the table reads off the critical path
+// between LDS exchanges.  LOCAL = true makes each entry opaque where a stage
+// uses it, so that its powers are formed inside that stage (fewer live
+// registers) instead of once for every stage and transform of the kernel.
+template <typename PL, typename T, bool LOCAL = false>
+struct TwPre {
+  static constexpr int NW = plan_twoff<PL>(PL::S) > 0 ? plan_twoff<PL>(PL::S) : 1;
+  cx<T> w[NW];
+};
+
+template <int N, typename PL, typename T, bool LOCAL>
+__device__ __forceinline__ void tw_preload(TwPre<PL, T, LOCAL>& t, int j, const cx<T>* __restrict__ tw) {
+  constexpr int RMAX = PL::RMAX, TT = PL::TT, S = PL::S;
+  static_for<1, S>([&](auto sI) {
+    constexpr int s = decltype(sI)::value;
+    constexpr int R = PL::R[s];
+    constexpr int U = RMAX / R;
+    constexpr int Ns = plan_ns<PL, s>();
+    constexpr int tstep = N / (Ns * R);
+#pragma unroll
+    for (int u = 0; u < U; ++u) t.w[plan_twoff<PL>(s) + u] = tw[((j + u * TT) & (Ns - 1)) * tstep];
+  });
+}
+
+template <typename PL, int s, typename T>
+__device__ __forceinline__ cx<T> tw_get(const cx<T>* __restrict__ tw, int u, int idx) {
+  (void)u;
+  return tw[idx];
+}
+// Value barrier: the compiler must assume x changed here (no code is emitted).
+#ifndef MAG_OPAQUE
+#define MAG_OPAQUE(x) asm volatile("" : "+v"(x))
+#endif
+
+template <typename PL, int s, typename T, bool LOCAL>
+__device__ __forceinline__ cx<T> tw_get(const TwPre<PL, T, LOCAL>& t, int u, int idx) {
+  (void)idx;
+  cx<T> w = t.w[plan_twoff<PL>(s) + u];
+  if constexpr (LOCAL) {
+    MAG_OPAQUE(w.x);
+    MAG_OPAQUE(w.y);
+  }
+  return w;
+}
+
 // Same transform as pencil_fft, with the LDS exchange holding interleaved
 // complex values (one access per element) and the inter-stage twiddles of a
 // thread formed from a single table entry per stage (twiddle_powers).
-template <int N, int DIR, typename P = Plan<N>, typename T, typename LIdx>
-__device__ __forceinline__ void pencil_fft_cx(cx<T>* v, int j, cx<T>* lds, LIdx lidx,
-                                              const cx<T>* __restrict__ tw) {
+// tw: the table itself or a TwPre set loaded by tw_preload for this j.
+template <int N, int DIR, typename P = Plan<N>, typename T, typename LIdx, typename TW>
+__device__ __forceinline__ void pencil_fft_cx(cx<T>* v, int j, cx<T>* lds, LIdx lidx, const TW& tw) {
   constexpr int RMAX = P::RMAX, TT = P::TT, S = P::S;
   if constexpr (S > 1) __syncthreads();   // LDS may still be read by a previous use
   static_for<0, S>([&](auto sI) {
@@ -259,7 +316,7 @@ __device__ __forceinline__ void pencil_fft_cx(cx<T>* v, int j, cx<T>* lds, LIdx 
       if constexpr (s > 0) {
         constexpr int tstep = N / (Ns * R);
         cx<T> wp[R];
-        twiddle_powers<R, T>(tw[k * tstep], wp);
+        twiddle_powers<R, T>(tw_get<P, s, T>(tw, u, k * tstep), wp);
 #pragma unroll
         for (int r = 1; r < R; ++r) a[r] = (DIR < 0) ? cmul(a[r], wp[r]) : cmulc(a[r], wp[r]);
       }

@@ -4,18 +4,18 @@
 //
 // Layouts (x fastest): g, dh/dt, G on nodes [ny][nx]; half spectrum stored
 // transposed, [kx][ny] with kx = nx/2 + 1, so that every pass reads and
-// writes contiguous runs.  One inner iteration:
-//   rows_fwd(H)   apply the pending shift A on free-space nodes, R2C of H - dh_e
-//   cols(K1)      y transform, multiply by 2/|k| (and 1/N), inverse y transform
-//   rows_inv(G)   C2R -> G, per-block sums of G over free space
-//   finalize      C = free-space mean of G                           (eq. (11))
-//   rows_fwd(G)   gdot = G - C, per-block sums of |gdot| over free space,
-//                 R2C of gdot masked to free space
-//   finalize      stop test of Sec. 2.3 (sets `done`)
-//   cols(K2)      |k|/2 multiplier
-//   rows_inv(upd) C2R -> V, H -= lambda V on free space, sums of H - dh_e over D
-//   finalize      A = sum / #free-space nodes                        (eq. (10), (12))
-// On convergence gdot = G - C is written to the output in double precision.
+// writes contiguous runs.  A right-hand side is
+//   stencil       e = rho(|j|) j on the edges, dh/dt = -curl e on inside
+//                 nodes (eq. (9)), and the shift A^0 of the first iterate
+//   rows_fwd(H)   R2C of H - dh_e, sums of w1 (H - dh_e)
+// then per inner iteration four passes (film_iteration below): the column
+// pass with 2/|k|, a fused row pass (C2R G, gdot = G - C with C from the w1
+// sums, R2C of gdot on free space), the column pass with |k|/2 (after the
+// stop decision on the |gdot| sums), and a fused row pass (update (12) of H on
+// free space, R2C of H - dh_e for the next iteration).  w1 = K1 1_out and
+// w2 = K2 1_out turn the free-space means of (10) and (11) into dot products
+// accumulated inside the row passes.  On exit gdot = G - C is written to the
+// output in double precision.
 #include <cmath>
 
 #include "ctx.h"
@@ -361,10 +361,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
         const T mut = (T)mu;
         X[ro + p] = mut;
         acc3 += fabs((double)mut);
+        const double wv = (double)w[ro + p];   // loaded with the flag, not after it
         if (out) {
           const double nu = (double)mut - c_new;
           acc += fabs(nu);
-          acc2 += (double)w[ro + p] * nu;
+          acc2 += wv * nu;
           u[e] = (T)nu;
         }
       } else {
@@ -419,7 +420,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // The free-space means C and A are not summed over the field itself: since
 // K1 and K2 are symmetric, sum_out K x = sum_D (K 1_out) x, so with
 // w = K 1_out precomputed they come from dot products taken one pass earlier.
-// MODE 6 (after the 2/|k| pass): G = C2R; write G; C = (sum of w1 (H - dh_e))
+// MODE 6 (after the 2/|k| pass): G = C2R; write G (if keep, i.e. unless a
+//        later iteration is known to follow); C = (sum of w1 (H - dh_e))
 //        / #out; gdot = G - C; sums over free space of |gdot| (out) and of
 //        w2 gdot (out2); R2C of gdot on free space.
 // MODE 7 (after the |k|/2 pass): V = C2R; on free space H <- H - lambda V - A
@@ -430,7 +432,7 @@ template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fused(T *__restrict__ X, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
                     const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
-                    FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it) {
+                    FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it, int keep) {
   if (it->done) return;
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
@@ -481,11 +483,12 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       if (!active) continue;
       const bool out = !(flags[ro + p] & 1);
       if constexpr (MODE == 6) {
-        X[ro + p] = val[e];
+        if (keep) X[ro + p] = val[e];
+        const double wv = (double)w[ro + p];   // loaded with the flag, not after it
         if (out) {
           const double gd = (double)val[e] - cst;
           acc += fabs(gd);
-          acc2 += (double)w[ro + p] * gd;
+          acc2 += wv * gd;
           u[e] = (T)gd;
         }
       } else {
@@ -635,6 +638,15 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // Column pass on the transposed spectrum: forward y transform of contiguous
 // columns, multiplier K(|k|) / N, inverse y transform.
 // which = 0: 2/|k| (eq. (7) solved for g, 0 at k = 0); which = 1: |k|/2 (eq. (12)).
+// The kx = 0 and kx = M (= nx/2) columns of the half spectrum of real rows are
+// real; they travel as the real and imaginary parts of one complex column,
+// processed by pencil 0 of block 0, so the pass covers kx - 1 = M pencils
+// (M divides evenly over the compute units at the usual sizes).  With
+// Z = a + i b (a, b real) and Zh its transform, the two spectra are
+// (Zh[k] + conj Zh[-k]) / 2 and (Zh[k] - conj Zh[-k]) / (2i), so the product
+// with the multipliers m0 (kx = 0) and mM (kx = M) is
+//   W[k] = (m0 + mM)/2 Zh[k] + (m0 - mM)/2 conj Zh[-k],
+// whose inverse transform is out0 + i outM.
 template <typename T, int NY>
 __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     film_cols(cx<T> *__restrict__ S, int kx, const double *__restrict__ k2x, const double *__restrict__ k2y,
@@ -661,28 +673,62 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     if (done) return;
   }
   const int pcol = threadIdx.x / TT, j = threadIdx.x % TT;
+  // FP64 forms the twiddle powers inside each stage (register budget of 4
+  // blocks per CU); FP32 leaves the compiler free to keep them for the
+  // inverse transform.
+  TwPre<PL, T, (sizeof(T) > 4)> twp;
+  tw_preload<NY, PL>(twp, j, tw);
   const int col = blockIdx.x * P + pcol;
-  const bool active = col < kx;
+  const bool active = col < kx - 1;
+  const bool pair_block = blockIdx.x == 0;          // uniform over the block
+  const bool packed = pair_block && pcol == 0;
   cx<T> *base = S + (long long)(active ? col : 0) * NY;
+  cx<T> *base_m = S + (long long)(kx - 1) * NY;
   cx<T> v[RMAX];
 #pragma unroll
-  for (int rho = 0; rho < RMAX; ++rho) v[rho] = active ? base[j + rho * TT] : cx<T>{(T)0, (T)0};
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int y = j + rho * TT;
+    if (packed) v[rho] = {base[y].x, base_m[y].x};
+    else v[rho] = active ? base[y] : cx<T>{(T)0, (T)0};
+  }
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
   auto lidx = [](int i) { return i + (i >> 4); };
-  pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, tw);
+  pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, twp);
   // multiplier in the compute precision: |k|^2 = kx^2 + ky^2
-  const T kxx = (T)k2x[active ? col : 0];
   const T c1 = (T)(2.0 * inv_n), c2 = (T)(0.5 * inv_n);
+  auto mult = [&](T kk2) -> T {
+    if (which == 0) return kk2 > (T)0 ? c1 * inv_sqrt(kk2) : (T)0;
+    return c2 * sqrt(kk2);
+  };
+  if (pair_block) {
+    __syncthreads();   // the transform's last LDS reads are done
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) xch[lidx(j + rho * TT)] = v[rho];
+    __syncthreads();
+  }
+  const T kxx = (T)k2x[active ? col : 0], kxm = (T)k2x[kx - 1];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
-    const T kk2 = kxx + (T)k2y[j + rho * TT];
-    T mult;
-    if (which == 0) mult = kk2 > (T)0 ? c1 * inv_sqrt(kk2) : (T)0;
-    else mult = c2 * sqrt(kk2);
-    v[rho] = scale(v[rho], mult);
+    const int k = j + rho * TT;
+    const T ky2 = (T)k2y[k];
+    const T m0 = mult(kxx + ky2);
+    if (packed) {
+      const cx<T> zm = conj(xch[lidx((NY - k) & (NY - 1))]);
+      const T mm = mult(kxm + ky2);
+      const T hp = (T)0.5 * (m0 + mm), hm = (T)0.5 * (m0 - mm);
+      v[rho] = {hp * v[rho].x + hm * zm.x, hp * v[rho].y + hm * zm.y};
+    } else {
+      v[rho] = scale(v[rho], m0);
+    }
   }
-  pencil_fft_cx<NY, +1, PL>(v, j, xch, lidx, tw);
-  if (active) {
+  pencil_fft_cx<NY, +1, PL>(v, j, xch, lidx, twp);
+  if (packed) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      base[j + rho * TT] = {v[rho].x, (T)0};
+      base_m[j + rho * TT] = {v[rho].y, (T)0};
+    }
+  } else if (active) {
 #pragma unroll
     for (int rho = 0; rho < RMAX; ++rho) base[j + rho * TT] = v[rho];
   }
@@ -964,7 +1010,7 @@ static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid)
 }
 
 template <typename T, int MODE>
-static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int kid) {
+static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int kid, int keep = 1) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, kid);
@@ -972,7 +1018,7 @@ static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int ki
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_fused<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
-                       f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it);
+                       f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it, keep);
   });
   return MAG_OK;
 }
@@ -1000,7 +1046,7 @@ static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)
   ProfScope ps(c, K_FILM_COLS);
   FILM_SWITCH_N(G.ny, {
     using CS = FilmColShape<NN, T>;
-    const int nblk = (G.kx + CS::P - 1) / CS::P;
+    const int nblk = (G.kx - 1 + CS::P - 1) / CS::P;   // the kx = 0 and kx = M columns share a pencil
     hipLaunchKernelGGL((film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x, f.k2y,
                        1.0 / (double)c->nnode, which, f.twY, pp, c->d_it, c->h_it);
   });
@@ -1025,7 +1071,10 @@ static int film_iteration(mag_ctx *c, double hde, int i) {
       (rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(nullptr, 0, pr.C), K_FILM_ROWS_FWD_H)))
     return rc;
   if ((rc = film_col<T>(c, 0))) return rc;
-  if ((rc = film_fused<T, 6>(c, f.G, f.w2, hde, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G))) return rc;
+  // G is read only after the last evaluation; at a fixed count that is known here
+  const int keep_g = c->fixed_iters <= 0 || i == c->fixed_iters - 1;
+  if ((rc = film_fused<T, 6>(c, f.G, f.w2, hde, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G, keep_g)))
+    return rc;
   if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, i)))) return rc;
   return film_fused<T, 7>(c, f.H, f.w1, hde, parts(pr.A, pr.nb, pr.C), K_FILM_ROWS_INV_UPD);
 }

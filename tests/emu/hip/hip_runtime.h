@@ -86,6 +86,7 @@ template <typename T>
 inline hipError_t hipMallocAsync(T **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
 inline float rsqrtf(float x) { return 1.0f / std::sqrt(x); }
 #define __align__(n) alignas(n)
+#define MAG_OPAQUE(x) asm volatile("" : "+m"(x))
 #define hipHostMallocCoherent 0x40000000u
 inline hipError_t hipHostMalloc(void *p, size_t n, unsigned = 0) { return hipMalloc(p, n); }
 inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
