@@ -79,21 +79,24 @@ __device__ __forceinline__ T film_edge_e(const double *__restrict__ g, const uin
 
 // dh_z/dt = -(d_x e_y - d_y e_x) at inside nodes (eq. (9)); free-space nodes
 // keep the warm start (or take dh_e/dt).  Each thread handles kStencilNpt
-// nodes 256 apart; one partial sum of H - dh_e over D per block.
+// nodes kStencilThreads apart; one partial sum of H - dh_e over D per block
+// (few enough blocks that every block of the next pass can add the partials
+// itself: 512 at 2048^2).
 constexpr int kStencilNpt = 8;
+constexpr int kStencilThreads = 1024;
 
 template <typename T>
-__global__ void __launch_bounds__(256) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+__global__ void __launch_bounds__(kStencilThreads) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
                                                     T *__restrict__ H, FilmGeom G, FilmLaw law, double hde,
                                                     int warm, double *__restrict__ part) {
-  __shared__ double red[4];
+  __shared__ double red[kStencilThreads / 64];
   const long long n = (long long)G.nx * G.ny;
-  const long long i0 = (long long)blockIdx.x * (256 * kStencilNpt) + threadIdx.x;
+  const long long i0 = (long long)blockIdx.x * (kStencilThreads * kStencilNpt) + threadIdx.x;
   double acc = 0.0;
 #pragma unroll 1
   for (int k = 0; k < kStencilNpt; ++k) {
-    const long long i = i0 + (long long)k * 256;
+    const long long i = i0 + (long long)k * kStencilThreads;
     if (i >= n) break;
     const int p = (int)(i % G.nx), q = (int)(i / G.nx);
     T h;
@@ -113,7 +116,7 @@ __global__ void __launch_bounds__(256) film_stencil(const double *__restrict__ g
     }
     acc += (double)h - hde;
   }
-  const double s = block_total<256>(acc, red);
+  const double s = block_total<kStencilThreads>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -202,7 +205,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   // MODE 0: the shift A of (10) from the previous update's sums (or the
   // stencil's, already reduced into it->A); MODE 1: C = free-space mean of G.
   double shift = 0.0;
-  if constexpr (MODE == 0) shift = pp.in ? parts_sum(pp.in, pp.nin) * it->inv_nout : it->A;
+  if constexpr (MODE == 0) {
+    // the shift A^0 from the stencil's per-block sums (or the value in it->A)
+    shift = pp.in ? parts_sum(pp.in, pp.nin) * it->inv_nout : it->A;
+    if (pp.in && blockIdx.x == 0 && threadIdx.x == 0) it->A = shift;
+  }
   if constexpr (MODE == 1) {
     shift = parts_sum(pp.in, pp.nin) * it->inv_nout;
     if (blockIdx.x == 0 && threadIdx.x == 0) it->C = shift;
@@ -420,8 +427,9 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // The free-space means C and A are not summed over the field itself: since
 // K1 and K2 are symmetric, sum_out K x = sum_D (K 1_out) x, so with
 // w = K 1_out precomputed they come from dot products taken one pass earlier.
-// MODE 6 (after the 2/|k| pass): G = C2R; write G (if keep, i.e. unless a
-//        later iteration is known to follow); C = (sum of w1 (H - dh_e))
+// MODE 6 (after the 2/|k| pass): G = C2R; write G (if keep) or, at the last
+//        evaluation of a fixed count, the result gdot = G - C to `res`
+//        (double); C = (sum of w1 (H - dh_e))
 //        / #out; gdot = G - C; sums over free space of |gdot| (out) and of
 //        w2 gdot (out2); R2C of gdot on free space.
 // MODE 7 (after the |k|/2 pass): V = C2R; on free space H <- H - lambda V - A
@@ -432,7 +440,8 @@ template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fused(T *__restrict__ X, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
                     const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
-                    FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it, int keep) {
+                    FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it, int keep,
+                    double *__restrict__ res) {
   if (it->done) return;
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
@@ -484,6 +493,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       const bool out = !(flags[ro + p] & 1);
       if constexpr (MODE == 6) {
         if (keep) X[ro + p] = val[e];
+        if (res) res[ro + p] = (double)val[e] - cst;
         const double wv = (double)w[ro + p];   // loaded with the flag, not after it
         if (out) {
           const double gd = (double)val[e] - cst;
@@ -1010,7 +1020,8 @@ static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid)
 }
 
 template <typename T, int MODE>
-static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int kid, int keep = 1) {
+static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int kid, int keep = 1,
+                      double *out = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfScope ps(c, kid);
@@ -1018,7 +1029,7 @@ static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int ki
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     hipLaunchKernelGGL((film_rows_fused<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
-                       f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it, keep);
+                       f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it, keep, out);
   });
   return MAG_OK;
 }
@@ -1055,27 +1066,30 @@ static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)
 
 // One inner iteration i (evaluation i of (11), then the update (12)), four
 // passes over the spectrum:
-//   (i = 0: rows_fwd  H: shift A^0, R2C of H - dh_e, sums of w1 (H - dh_e))
+//   (i = 0: rows_fwd  H: shift A^0 from the stencil sums, R2C of H - dh_e,
+//                     sums of w1 (H - dh_e))
 //   cols       2/|k|
 //   fused 6    G, C from the w1 sums, gdot = G - C, sums of |gdot| and of
 //              w2 gdot over free space, R2C of gdot on free space
 //   cols       stop decision on the |gdot| sums, then |k|/2
 //   fused 7    H <- H - lambda V - A on free space (A from the w2 sums),
 //              sums of w1 (H - dh_e), R2C of H - dh_e (next iteration)
+// At a fixed count the last evaluation writes gdot to `out` itself and the
+// update that no evaluation would use is not launched (the column pass still
+// records the residual and the count); otherwise G is kept for film_out.
 template <typename T>
-static int film_iteration(mag_ctx *c, double hde, int i) {
+static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
   const FilmPtrs<T> f = fptrs<T>(c);
   const PartRegions pr = film_regions<T>(c);
   int rc;
-  if (i == 0 &&
-      (rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(nullptr, 0, pr.C), K_FILM_ROWS_FWD_H)))
-    return rc;
+  if (i == 0 && (rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(pr.X, nbs, pr.C), K_FILM_ROWS_FWD_H))) return rc;
   if ((rc = film_col<T>(c, 0))) return rc;
-  // G is read only after the last evaluation; at a fixed count that is known here
-  const int keep_g = c->fixed_iters <= 0 || i == c->fixed_iters - 1;
-  if ((rc = film_fused<T, 6>(c, f.G, f.w2, hde, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G, keep_g)))
+  const bool last_fixed = c->fixed_iters > 0 && i == c->fixed_iters - 1;
+  if ((rc = film_fused<T, 6>(c, f.G, f.w2, hde, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G,
+                             c->fixed_iters <= 0 ? 1 : 0, last_fixed ? out : nullptr)))
     return rc;
   if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, i)))) return rc;
+  if (last_fixed) return MAG_OK;
   return film_fused<T, 7>(c, f.H, f.w1, hde, parts(pr.A, pr.nb, pr.C), K_FILM_ROWS_INV_UPD);
 }
 
@@ -1099,14 +1113,14 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   law.jc0 = c->jc0;
   law.has_jc = c->has_jc_map ? 1 : 0;
   const long long n = c->nnode;
-  const int nbs = (int)((n + 256 * kStencilNpt - 1) / (256 * kStencilNpt));   // stencil blocks
+  const int nbs = (int)((n + kStencilThreads * kStencilNpt - 1) / (kStencilThreads * kStencilNpt));   // stencil blocks
   {
     ProfScope ps(c, K_FILM_STENCIL);
-    hipLaunchKernelGGL((film_stencil<T>), dim3(nbs), dim3(256), 0, c->stream, state, c->d_mat, c->d_flags,
-                       reinterpret_cast<const T *>(c->d_jc), f.H, G, law, hde, c->warm_valid ? 1 : 0, c->d_part);
+    hipLaunchKernelGGL((film_stencil<T>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat, c->d_flags,
+                       reinterpret_cast<const T *>(c->d_jc), f.H, G, law, hde, c->warm_valid ? 1 : 0,
+                       film_regions<T>(c).X);
   }
-  int rc = run_finalize_mean(c, nbs, 1);   // A^0
-  if (rc) return rc;
+  int rc = MAG_OK;
   MAG_HIP(c, hipGetLastError());
   const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
   int issued = 0;
@@ -1116,13 +1130,14 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
     const int k = block < kmax - issued ? block : kmax - issued;
     for (int i = 0; i < k; ++i) {
       c->cur_iter = issued + i;
-      if ((rc = film_iteration<T>(c, hde, issued + i))) return rc;
+      if ((rc = film_iteration<T>(c, hde, issued + i, nbs, out))) return rc;
     }
     c->cur_iter = -1;
     issued += k;
     // out = G - C, enqueued before the poll: right whenever this block ends
-    // the iteration (it is enqueued again after a further block otherwise)
-    {
+    // the iteration (it is enqueued again after a further block otherwise);
+    // at a fixed count the last evaluation has written it already
+    if (c->fixed_iters <= 0) {
       ProfScope ps(c, K_MISC);
       hipLaunchKernelGGL((film_out<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, f.G, out, n,
                          c->d_it);
