@@ -141,6 +141,14 @@ struct FilmRowShape {
   static constexpr int STG = 2 * (M + 1) * SP;        // T entries of the tile
   static constexpr int LDS_T = XCH > STG ? XCH : STG;
   static constexpr int THREADS = P * TT;
+  // Waves per SIMD that a square grid (ny = 2M rows) needs resident for its
+  // row blocks to run in one round on 256 CUs, capped by what LDS (160 KB
+  // per CU) admits: the register budget handed to the compiler.
+  static constexpr int BLOCKS_LDS = (160 * 1024) / (LDS_T * (int)sizeof(T) + 1024);
+  static constexpr int BLOCKS_SQ = ((2 * M + P - 1) / P + 255) / 256;
+  static constexpr int BLOCKS_CU = BLOCKS_SQ < BLOCKS_LDS ? BLOCKS_SQ : BLOCKS_LDS;
+  static constexpr int WAVES_EU_RAW = BLOCKS_CU * ((THREADS + 63) / 64) / 4;
+  static constexpr int WAVES_EU = WAVES_EU_RAW < 1 ? 1 : (WAVES_EU_RAW > 8 ? 8 : WAVES_EU_RAW);
   static_assert(THREADS <= 1024, "row block too large");
   static_assert(LDS_T * sizeof(T) <= 150 * 1024, "row block LDS too large");
 };
@@ -427,7 +435,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // The free-space means C and A are not summed over the field itself: since
 // K1 and K2 are symmetric, sum_out K x = sum_D (K 1_out) x, so with
 // w = K 1_out precomputed they come from dot products taken one pass earlier.
-// MODE 6 (after the 2/|k| pass): G = C2R; write G (if keep) or, at the last
+// MODE 6 (after the 2/|k| pass; w = w2, NaN on film nodes, so the flags are
+//        not read): G = C2R; write G (if keep) or, at the last
 //        evaluation of a fixed count, the result gdot = G - C to `res`
 //        (double); C = (sum of w1 (H - dh_e))
 //        / #out; gdot = G - C; sums over free space of |gdot| (out) and of
@@ -438,6 +447,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 //        over D (out, the next C); R2C of H - dh_e.
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
+    MAG_WAVES_PER_EU(FilmRowShape<M, T>::WAVES_EU)
     film_rows_fused(T *__restrict__ X, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
                     const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
                     FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it, int keep,
@@ -454,6 +464,19 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
+  // MODE 6: the weights w2 of this thread's nodes 2m, 2m+1 (m = j + rho TT),
+  // NaN on film nodes (so they carry the free-space flag too), loaded first
+  // so that their latency overlaps the tile load and the complex-to-real
+  // transform.
+  T wpre[RMAX][2];
+  if constexpr (MODE == 6) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const long long o = ro + 2 * (j + rho * TT);
+      wpre[rho][0] = active ? w[o] : (T)0;
+      wpre[rho][1] = active ? w[o + 1] : (T)0;
+    }
+  }
   cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
   for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
     const int k = idx / P, r = idx % P;
@@ -490,11 +513,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     for (int e = 0; e < 2; ++e) {
       const int p = 2 * (j + rho * TT) + e;
       if (!active) continue;
-      const bool out = !(flags[ro + p] & 1);
       if constexpr (MODE == 6) {
+        const double wv = (double)wpre[rho][e];
+        const bool out = !isnan(wv);
         if (keep) X[ro + p] = val[e];
         if (res) res[ro + p] = (double)val[e] - cst;
-        const double wv = (double)w[ro + p];   // loaded with the flag, not after it
         if (out) {
           const double gd = (double)val[e] - cst;
           acc += fabs(gd);
@@ -502,6 +525,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           u[e] = (T)gd;
         }
       } else {
+        const bool out = !(flags[ro + p] & 1);
         T h = X[ro + p];
         if (out) {
           h = (T)((double)h - lam * (double)val[e] - cst);
@@ -1386,6 +1410,17 @@ __global__ void __launch_bounds__(256) from_double_k(const double *__restrict__ 
 }  // namespace
 
 // tmp: device double[2n], the indicator in the first half.
+// w = K 1_out in the compute precision; with mark_film, film nodes hold a
+// NaN instead, so that a pass that needs w only on free space reads its
+// free-space flag from w itself.
+template <typename T>
+__global__ void __launch_bounds__(256) weights_k(const double *__restrict__ src, T *__restrict__ dst,
+                                                 const uint8_t *__restrict__ flags, int mark_film, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = (mark_film && (flags[i] & 1)) ? (T)NAN : (T)src[i];
+}
+
 template <typename T>
 static int film_weights_t(mag_ctx *c, double *tmp) {
   const long long n = c->nnode;
@@ -1398,8 +1433,8 @@ static int film_weights_t(mag_ctx *c, double *tmp) {
     if ((rc = film_col<T>(c, which))) return rc;
     if ((rc = film_inv<T, 2>(c, nullptr, tmp + n, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
     ProfScope ps(c, K_MISC);
-    hipLaunchKernelGGL((from_double_k<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, tmp + n,
-                       w + which * n, n);
+    hipLaunchKernelGGL((weights_k<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, tmp + n,
+                       w + which * n, c->d_flags, which, n);
   }
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;

@@ -3,6 +3,12 @@
 #pragma once
 #include "fft.h"
 
+// Minimum resident waves per SIMD promised to the compiler (it then keeps the
+// register count within 512 / n).
+#ifndef MAG_WAVES_PER_EU
+#define MAG_WAVES_PER_EU(...) __attribute__((amdgpu_waves_per_eu(__VA_ARGS__)))
+#endif
+
 namespace mag {
 
 constexpr int kLdsBudget = 64 * 1024;   // bytes of LDS per work-group for FFT scratch

@@ -65,6 +65,7 @@ using std::exp;
 using std::fabs;
 using std::fmax;
 using std::isfinite;
+using std::isnan;
 using std::log;
 using std::sqrt;
 
@@ -87,6 +88,7 @@ inline hipError_t hipMallocAsync(T **p, size_t n, hipStream_t) { return hipMallo
 inline float rsqrtf(float x) { return 1.0f / std::sqrt(x); }
 #define __align__(n) alignas(n)
 #define MAG_OPAQUE(x) asm volatile("" : "+m"(x))
+#define MAG_WAVES_PER_EU(...)
 #define hipHostMallocCoherent 0x40000000u
 inline hipError_t hipHostMalloc(void *p, size_t n, unsigned = 0) { return hipMalloc(p, n); }
 inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
