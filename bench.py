@@ -13,10 +13,11 @@ work) on a Bean-like snapshot already resident in HBM.  A fixed count is used
 because on this snapshot, which is not a state reached by time integration,
 the iteration with lambda = 0.7 does not reach the stop test at 2048^2.
 Prints one JSON line.  The throughput comes from a loop without any
-instrumentation; per-kernel durations come from HIP events that the library
-records on its own stream in two further loops of the same run: around every
-launch (the breakdown), and around the dominant kernel only (its mean
-duration, the roofline figure).
+instrumentation; per-kernel durations come from a further loop of the same
+run in which the library attaches HIP start/stop events to the dispatch of
+each transform kernel (hipExtLaunchKernelGGL, so no marker packets are timed
+with the kernel): the breakdown, and the mean duration of the dominant kernel
+(the roofline figure).
 """
 import argparse
 import json
@@ -64,27 +65,37 @@ def film_inputs(mask, t_snap):
     return wl, mat, jc, g
 
 
-def alg_bytes(kernel, n, kx, ny, prec, has_jc=True):
-    """Algorithmic HBM bytes of one launch: every input read once, every output
-    written once (n nodes, kx*ny half-spectrum entries)."""
+def free_nodes(mat):
+    """Free-space nodes of a film material: a node is inside when the four
+    cells around it are film."""
+    F = mat != 0
+    inside = F & np.roll(F, 1, axis=1) & np.roll(F, 1, axis=0) & np.roll(np.roll(F, 1, axis=0), 1, axis=1)
+    return int(F.size - inside.sum())
+
+
+def alg_bytes(kernel, n, kx, ny, prec, iters, n_out, has_jc=True):
+    """Algorithmic HBM bytes per launch of each kernel of a fixed-count
+    right-hand side (every input read once, every output written once; n
+    nodes, n_out of them in free space, kx*ny half-spectrum entries, `iters`
+    inner iterations), averaged over that kernel's launches in one call."""
     sc = 16 if prec == "fp64" else 8      # complex
-    sr = 8 if prec == "fp64" else 4       # iterate
+    sr = 8 if prec == "fp64" else 4       # iterate, weights
     ns = kx * ny
+    K = iters
     table = {
-        # g (double), material, flags, jc, H out
-        "film_stencil": 8 * n + 2 * n + (sr * n if has_jc else 0) + sr * n,
-        # H in, flags, H out (shifted free-space part counted whole), spectrum out
-        "film_rows_fwd_h": sr * n + n + sr * n + sc * ns,
-        # spectrum in and out
-        "film_cols": 2 * sc * ns,
-        # spectrum in, flags, G out
-        "film_rows_inv_g": sc * ns + n + sr * n,
-        # G in, flags, spectrum out
-        "film_rows_fwd_g": sr * n + n + sc * ns,
-        # spectrum in, flags, H in, H out
-        "film_rows_inv_upd": sc * ns + n + 2 * sr * n,
+        # g (double), material and jc around inside nodes; flags; H out
+        "film_stencil": (8 + 1 + (sr if has_jc else 0)) * (n - n_out) + n + sr * n,
+        # H, flags, w1 in; H out on free space; spectrum out
+        "film_rows_fwd_h": 2 * sr * n + n + sr * n_out + sc * ns,
+        # 2K launches, the last one takes only the stop decision
+        "film_cols": (2 * K - 1) * 2 * sc * ns / (2 * K),
+        # spectrum in and out, w2; the last of the K launches writes dh/dt (double)
+        "film_rows_inv_g": 2 * sc * ns + sr * n + 8 * n / K,
+        # K - 1 launches: spectrum in and out, w1, H in, H out on free space
+        "film_rows_inv_upd": 2 * sc * ns + 2 * sr * n + sr * n_out,
     }
-    return table.get(kernel)
+    v = table.get(kernel)
+    return int(round(v)) if v is not None else None
 
 
 def sources_hash():
@@ -98,17 +109,18 @@ def sources_hash():
 
 
 def recorded_traffic(kernel, prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if there is none for this kernel or the sources changed since."""
+    """HBM bytes per launch from the committed rocprofv3 counter summaries
+    (a line `traffic <kernel> <prec> bytes_per_launch=<B> sources_sha256_16=<H>`
+    in a file under profiles/), or None if there is none for this kernel or the
+    kernel sources changed since."""
+    import glob
     import re
-    path = os.path.join(ROOT, "profiles", "%s_film2048_%s.md" % (kernel, prec))
-    if not os.path.exists(path):
-        return None
-    m = re.search(r"traffic %s %s bytes_per_launch=(\d+) sources_sha256_16=([0-9a-f]+)" % (kernel, prec),
-                  open(path).read())
-    if not m or m.group(2) != sources_hash():
-        return None
-    return int(m.group(1))
+    pat = re.compile(r"traffic %s %s bytes_per_launch=(\d+) sources_sha256_16=([0-9a-f]+)" % (kernel, prec))
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        m = pat.search(open(path).read())
+        if m:
+            return int(m.group(1)) if m.group(2) == sources_hash() else None
+    return None
 
 
 def make_ctx(prec, wl, mat, jc, fixed=0):
@@ -126,10 +138,11 @@ def make_ctx(prec, wl, mat, jc, fixed=0):
 
 
 def run_gpu(prec, wl, mat, jc, g, steps, warmup, t, fixed=0):
-    """Three loops of `steps` right-hand sides on the same snapshot: the timed
-    loop without any instrumentation (the throughput), then one with HIP
-    events around every launch (the per-kernel breakdown) and one with events
-    around the dominant kernel only (its mean duration for the roofline).
+    """Loops of `steps` right-hand sides on the same snapshot: the timed loop
+    without any instrumentation (the throughput), the same calls enqueued
+    back to back, and one with HIP events on every launch (the per-kernel
+    breakdown, and the mean duration of the dominant kernel for the
+    roofline), then the VJP.
     Every call restarts the inner iteration from h_e (no warm start), so with a
     fixed inner count every call does the same work."""
     import torch
@@ -160,15 +173,14 @@ def run_gpu(prec, wl, mat, jc, g, steps, warmup, t, fixed=0):
     ctx.rhs_status()
     torch.cuda.synchronize()
     dt_stream = time.perf_counter() - t1
+    # per-kernel durations: each transform kernel is launched with start and
+    # stop events attached to its own dispatch (hipExtLaunchKernelGGL)
     ctx.prof_enable(True)
-    loop(max(steps // 2, 1))
+    loop(steps)
     prof_all = ctx.prof_read()
     ctx.prof_enable(False)
-    dominant = max((k for k in prof_all if alg_bytes(k, 1, 1, 1, prec)), key=lambda k: prof_all[k][1])
-    ctx.prof_enable(True, only=dominant)
-    loop(steps)
-    prof_dom = ctx.prof_read()
-    ctx.prof_enable(False)
+    dominant = max((k for k in prof_all if alg_bytes(k, 1, 1, 1, prec, 4, 1)), key=lambda k: prof_all[k][1])
+    prof_dom = {dominant: prof_all[dominant]}
     # VJP of the same right-hand side (same fixed count), timed like the forward
     ybar = torch.ones_like(state)
     gbar = torch.empty_like(state)
@@ -210,10 +222,10 @@ def cpu_baseline(wl, mat, jc, g, t, iters):
                        "2048^2 snapshot, median %.2f s" % (iters, med))
 
 
-def kernel_table(prof, n, kx, ny, prec):
+def kernel_table(prof, n, kx, ny, prec, iters, n_out):
     rows = {}
     for k, (cnt, ms) in prof.items():
-        ab = alg_bytes(k, n, kx, ny, prec)
+        ab = alg_bytes(k, n, kx, ny, prec, iters, n_out)
         avg = ms / cnt * 1e-3
         rows[k] = dict(launches=cnt, avg_us=round(avg * 1e6, 2),
                        GBps=round(ab / avg / 1e9, 1) if ab else None)
@@ -243,11 +255,12 @@ def main():
     wl, mat, jc, g = inputs[a.mask]
     nx, ny = wl["n"]
     n, kx = nx * ny, nx // 2 + 1
+    n_out = free_nodes(mat)
     m = res[(a.mask, "mixed")]
     kern = m["dominant"]
     cnt, tot = m["prof_dom"]
     avg_s = tot / cnt * 1e-3
-    ab = alg_bytes(kern, n, kx, ny, "mixed")
+    ab = alg_bytes(kern, n, kx, ny, "mixed", a.iters, n_out)
     achieved = ab / avg_s / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kern, "mixed"), kernel=kern,
@@ -262,7 +275,7 @@ def main():
                             bulk_256="not measured: 3D path held off the GPU"),
                 inner_iters=round(m["inner_iters"], 3),
                 value_enqueued_back_to_back=round(m["value_stream"], 3), roofline=roof,
-                kernels_mixed=kernel_table(m["prof"], n, kx, ny, "mixed"))
+                kernels_mixed=kernel_table(m["prof"], n, kx, ny, "mixed", a.iters, n_out))
     others = {}
     for (mask, prec), r in res.items():
         if (mask, prec) == (a.mask, "mixed"):
@@ -278,7 +291,7 @@ def main():
         # accuracy of the mixed form against the FP64 form on the same snapshot
         d = m["out"] - f64["out"]
         line["mixed_vs_fp64_rel_l2"] = float(np.linalg.norm(d) / max(np.linalg.norm(f64["out"]), 1e-300))
-        line["kernels_fp64"] = kernel_table(f64["prof"], n, kx, ny, "fp64")
+        line["kernels_fp64"] = kernel_table(f64["prof"], n, kx, ny, "fp64", a.iters, n_out)
     line["adjoint_forward_ratio"] = round(m["vjp_ms"] / m["ms_per_step"], 3)
     line["adjoint_ms_per_rhs"] = round(m["vjp_ms"], 4)
     if not a.no_cpu:

@@ -209,10 +209,13 @@ int mag_observe_vjp(mag_ctx *ctx, const double *hz_bar, double *state_bar);
 const char *mag_last_error(const mag_ctx *ctx);
 
 /* ---- instrumentation (timing of individual kernels, for benchmarks) ----
- * mag_prof_enable(ctx, 1) records a pair of HIP events around every kernel
- * launch on the context's stream; mag_prof_enable(ctx, 2 + id) only around
- * launches of kernel `id` (the events cost host time per launch);
- * mag_prof_enable(ctx, 0) stops and clears.
+ * mag_prof_enable(ctx, 1) times every kernel launch on the context's stream:
+ * the film transform and stencil kernels (one launch per record) through
+ * HIP start/stop events attached to their own dispatch, the other records
+ * through a pair of event records around their launches (which adds the
+ * markers' own time); mag_prof_enable(ctx, 2 + id) times launches of kernel
+ * `id` only (the events cost host time per launch); mag_prof_enable(ctx, 0)
+ * stops and clears.
  * mag_prof_read sums the recorded durations of kernel `id` (synchronising the
  * stream): *count launches, *total_ms milliseconds.  Launches that found the
  * iteration already converged and returned at once are not recorded.

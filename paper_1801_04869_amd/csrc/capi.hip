@@ -116,6 +116,31 @@ void prof_end(mag_ctx *c, ProfRec *r) {
   c->prof.push_back(*r);
 }
 
+void prof_launch_begin(mag_ctx *c, int kid, ProfRec *r) {
+  r->a = r->b = nullptr;
+  r->kid = kid;
+  r->iter = c->cur_iter;
+  if (c->debug_sync) {
+    fprintf(stderr, "[magfft] launch %s (iteration %d)\n", kNames[kid], c->cur_iter);
+    fflush(stderr);
+  }
+  if (!c->prof_on || (c->prof_only >= 0 && kid != c->prof_only)) return;
+  r->a = pool_get(c);
+  r->b = r->a ? pool_get(c) : nullptr;
+  if (!r->b) r->a = nullptr;
+}
+
+void prof_launch_end(mag_ctx *c, ProfRec *r) {
+  if (c->debug_sync) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    fprintf(stderr, "[magfft]   %s -> %s\n", kNames[r->kid], e == hipSuccess ? "ok" : hipGetErrorString(e));
+    fflush(stderr);
+  }
+  if (!c->prof_on || !r->a || !r->b) return;
+  c->prof.push_back(*r);
+}
+
 // Called after an RHS: launches of iterations >= iters_done found `done` set
 // and returned at once; drop them (they are the newest records).
 void prof_drop_after(mag_ctx *c, int iters_done) {

@@ -1,6 +1,7 @@
 // Internal context of the magfft library (host side).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -162,6 +163,23 @@ struct ProfScope {
   ProfScope(mag_ctx *c_, int kid) : c(c_) { prof_begin(c, kid, &r); }
   ~ProfScope() { prof_end(c, &r); }
 };
+
+// Timing of a single kernel launch by the dispatch itself: the launch goes
+// through hipExtLaunchKernelGGL with this record's events (null when the
+// kernel is not being profiled), so the elapsed time is the kernel's own
+// execution, without the marker packets that separate event records add.
+void prof_launch_begin(mag_ctx *c, int kid, ProfRec *r);
+void prof_launch_end(mag_ctx *c, ProfRec *r);
+struct ProfLaunch {
+  mag_ctx *c;
+  ProfRec r;
+  ProfLaunch(mag_ctx *c_, int kid) : c(c_) { prof_launch_begin(c, kid, &r); }
+  ~ProfLaunch() { prof_launch_end(c, &r); }
+  hipEvent_t start() const { return r.a; }
+  hipEvent_t stop() const { return r.b; }
+};
+#define MAG_TIMED_LAUNCH(pl, K, G, B, S, STREAM, ...) \
+  hipExtLaunchKernelGGL(K, G, B, S, STREAM, (pl).start(), (pl).stop(), 0, __VA_ARGS__)
 
 // dimension-specific drivers
 int film_alloc(mag_ctx *c);

@@ -223,7 +223,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     if (blockIdx.x == 0 && threadIdx.x == 0) it->C = shift;
   }
   if constexpr (MODE == 5) shift = it->A;
-  double acc = 0.0;
+  double acc = 0.0, acc_film = 0.0;
   cx<T> v[RMAX];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
@@ -234,12 +234,17 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       if (!active) continue;
       if constexpr (MODE == 0) {
         T h = X[ro + p];
-        if (!(flags[ro + p] & 1)) {
+        const bool film = flags[ro + p] & 1;
+        if (!film) {
           h = (T)((double)h - shift);
           X[ro + p] = h;
         }
         val[e] = (T)((double)h - hde);
-        if (w1) acc += (double)w1[ro + p] * ((double)h - hde);
+        if (w1) {
+          const double t = (double)w1[ro + p] * ((double)h - hde);
+          acc += t;
+          if (film) acc_film += t;
+        }
       } else if constexpr (MODE == 1) {
         const double gd = (double)X[ro + p] - shift;
         if (!(flags[ro + p] & 1)) {
@@ -289,6 +294,14 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   if constexpr (MODE == 1) {
     const double sblk = block_total<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) pp.out[blk] = sblk;
+  }
+  if constexpr (MODE == 0) {
+    // the film part of the sums stays fixed while the iteration only
+    // changes H on free space: per-block values for the update passes
+    if (pp.out2) {
+      const double sf = block_total<RS::THREADS>(acc_film, red + RS::THREADS / 64);
+      if (threadIdx.x == 0) pp.out2[blk] = sf;
+    }
   }
   if constexpr (MODE == 0 || MODE == 5) {
     if (pp.out) {
@@ -441,10 +454,12 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 //        (double); C = (sum of w1 (H - dh_e))
 //        / #out; gdot = G - C; sums over free space of |gdot| (out) and of
 //        w2 gdot (out2); R2C of gdot on free space.
-// MODE 7 (after the |k|/2 pass): V = C2R; on free space H <- H - lambda V - A
-//        with A = -lambda (sum of w2 gdot) / #out, the shift that restores
-//        (10) (sum_D (H - dh_e) was 0 before the update); sums of w1 (H - dh_e)
-//        over D (out, the next C); R2C of H - dh_e.
+// MODE 7 (after the |k|/2 pass; w = w1, NaN on film nodes): V = C2R; on
+//        free space H <- H - lambda V - A with A = -lambda (sum of w2 gdot) /
+//        #out, the shift that restores (10) (sum_D (H - dh_e) was 0 before
+//        the update); sums of w1 (H - dh_e) over D (out, the next C: the free
+//        space part here plus the fixed film part per block, read from
+//        out2); R2C of H - dh_e.
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     MAG_WAVES_PER_EU(FilmRowShape<M, T>::WAVES_EU)
@@ -464,18 +479,15 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
-  // MODE 6: the weights w2 of this thread's nodes 2m, 2m+1 (m = j + rho TT),
-  // NaN on film nodes (so they carry the free-space flag too), loaded first
-  // so that their latency overlaps the tile load and the complex-to-real
-  // transform.
+  // The weights of this thread's nodes 2m, 2m+1 (m = j + rho TT), NaN on
+  // film nodes (so they carry the free-space flag too), loaded first so that
+  // their latency overlaps the tile load and the complex-to-real transform.
   T wpre[RMAX][2];
-  if constexpr (MODE == 6) {
 #pragma unroll
-    for (int rho = 0; rho < RMAX; ++rho) {
-      const long long o = ro + 2 * (j + rho * TT);
-      wpre[rho][0] = active ? w[o] : (T)0;
-      wpre[rho][1] = active ? w[o + 1] : (T)0;
-    }
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const long long o = ro + 2 * (j + rho * TT);
+    wpre[rho][0] = active ? w[o] : (T)0;
+    wpre[rho][1] = active ? w[o + 1] : (T)0;
   }
   cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
   for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
@@ -525,15 +537,16 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           u[e] = (T)gd;
         }
       } else {
-        const bool out = !(flags[ro + p] & 1);
+        // free space: update (12) and the free-space part of the w1 sums
+        // (the film part, fixed, is added per block below)
+        const double wv = (double)wpre[rho][e];
         T h = X[ro + p];
-        if (out) {
+        if (!isnan(wv)) {
           h = (T)((double)h - lam * (double)val[e] - cst);
           X[ro + p] = h;
+          acc += wv * ((double)h - hde);
         }
-        const double d = (double)h - hde;
-        acc += (double)w[ro + p] * d;
-        u[e] = (T)d;
+        u[e] = (T)((double)h - hde);
       }
     }
     v[rho] = {u[0], u[1]};
@@ -565,7 +578,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
   }
   const double s1 = block_total<RS::THREADS>(acc, red);
-  if (threadIdx.x == 0) pp.out[blk] = s1;
+  if constexpr (MODE == 6) {
+    if (threadIdx.x == 0) pp.out[blk] = s1;
+  } else {
+    if (threadIdx.x == 0) pp.out[blk] = s1 + pp.out2[blk];
+  }
   if constexpr (MODE == 6) {
     const double s2 = block_total<RS::THREADS>(acc2, red + RS::THREADS / 64);
     if (threadIdx.x == 0) pp.out2[blk] = s2;
@@ -958,7 +975,8 @@ struct FilmPtrs {
   cx<T> *S;
   const cx<T> *twM, *twY, *twN;
   const double *k2x, *k2y;
-  T *w1, *w2;   // K1 1_out and K2 1_out
+  T *w1, *w2;   // K1 1_out and K2 1_out (w2: NaN on film nodes)
+  T *w1f;       // K1 1_out with NaN on film nodes
 };
 
 template <typename T>
@@ -975,6 +993,7 @@ static FilmPtrs<T> fptrs(mag_ctx *c) {
   f.k2y = c->d_sym + c->sym_off[1];
   f.w1 = reinterpret_cast<T *>(c->d_w);
   f.w2 = f.w1 ? f.w1 + c->nnode : nullptr;
+  f.w1f = f.w1 ? f.w1 + 2 * c->nnode : nullptr;
   return f;
 }
 
@@ -989,9 +1008,13 @@ static int film_row_blocks(mag_ctx *c) {
 
 // Regions of d_part used by the passes of one iteration (nb row blocks each).
 struct PartRegions {
-  double *C, *R, *A, *X;
+  double *C, *R, *A, *X, *F;
   int nb;
 };
+
+static int film_stencil_blocks(mag_ctx *c) {
+  return (int)((c->nnode + kStencilThreads * kStencilNpt - 1) / (kStencilThreads * kStencilNpt));
+}
 
 template <typename T>
 static PartRegions film_regions(mag_ctx *c) {
@@ -1000,7 +1023,8 @@ static PartRegions film_regions(mag_ctx *c) {
   r.C = c->d_part;
   r.R = c->d_part + r.nb;
   r.A = c->d_part + 2 * r.nb;
-  r.X = c->d_part + 3 * r.nb;
+  r.X = c->d_part + 3 * r.nb;   // stencil partials (film_stencil_blocks of them)
+  r.F = r.X + film_stencil_blocks(c);
   return r;
 }
 
@@ -1018,11 +1042,11 @@ template <typename T, int MODE>
 static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, int kid) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
-  ProfScope ps(c, kid);
+  ProfLaunch ps(c, kid);
   FILM_SWITCH_M(G.nx / 2, {
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
-    hipLaunchKernelGGL((film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
+    MAG_TIMED_LAUNCH(ps, (film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
                        c->d_flags, f.S, f.twM, f.twN, G, hde, pp, c->d_it,
                        ((MODE == 0 || MODE == 5) && pp.out) ? (const T *)f.w1 : (const T *)nullptr);
   });
@@ -1033,11 +1057,11 @@ template <typename T, int MODE>
 static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
-  ProfScope ps(c, kid);
+  ProfLaunch ps(c, kid);
   FILM_SWITCH_M(G.nx / 2, {
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
-    hipLaunchKernelGGL((film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
+    MAG_TIMED_LAUNCH(ps, (film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
                        c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it);
   });
   return MAG_OK;
@@ -1048,11 +1072,11 @@ static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int ki
                       double *out = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
-  ProfScope ps(c, kid);
+  ProfLaunch ps(c, kid);
   FILM_SWITCH_M(G.nx / 2, {
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
-    hipLaunchKernelGGL((film_rows_fused<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
+    MAG_TIMED_LAUNCH(ps, (film_rows_fused<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
                        f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it, keep, out);
   });
   return MAG_OK;
@@ -1062,11 +1086,11 @@ template <typename T, int MODE>
 static int film_adj(mag_ctx *c, T *X, const T *w, AdjParts pp) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
-  ProfScope ps(c, K_VJP);
+  ProfLaunch ps(c, K_VJP);
   FILM_SWITCH_M(G.nx / 2, {
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
-    hipLaunchKernelGGL((film_rows_adj<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
+    MAG_TIMED_LAUNCH(ps, (film_rows_adj<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
                        f.S, w, f.twM, f.twN, G, c->lambda, pp, c->d_it);
   });
   return MAG_OK;
@@ -1078,11 +1102,11 @@ template <typename T>
 static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
-  ProfScope ps(c, K_FILM_COLS);
+  ProfLaunch ps(c, K_FILM_COLS);
   FILM_SWITCH_N(G.ny, {
     using CS = FilmColShape<NN, T>;
     const int nblk = (G.kx - 1 + CS::P - 1) / CS::P;   // the kx = 0 and kx = M columns share a pencil
-    hipLaunchKernelGGL((film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x, f.k2y,
+    MAG_TIMED_LAUNCH(ps, (film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x, f.k2y,
                        1.0 / (double)c->nnode, which, f.twY, pp, c->d_it, c->h_it);
   });
   return MAG_OK;
@@ -1106,7 +1130,8 @@ static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
   const FilmPtrs<T> f = fptrs<T>(c);
   const PartRegions pr = film_regions<T>(c);
   int rc;
-  if (i == 0 && (rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(pr.X, nbs, pr.C), K_FILM_ROWS_FWD_H))) return rc;
+  if (i == 0 && (rc = film_fwd<T, 0>(c, f.H, nullptr, hde, parts(pr.X, nbs, pr.C, pr.F), K_FILM_ROWS_FWD_H)))
+    return rc;
   if ((rc = film_col<T>(c, 0))) return rc;
   const bool last_fixed = c->fixed_iters > 0 && i == c->fixed_iters - 1;
   if ((rc = film_fused<T, 6>(c, f.G, f.w2, hde, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G,
@@ -1114,7 +1139,7 @@ static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
     return rc;
   if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, i)))) return rc;
   if (last_fixed) return MAG_OK;
-  return film_fused<T, 7>(c, f.H, f.w1, hde, parts(pr.A, pr.nb, pr.C), K_FILM_ROWS_INV_UPD);
+  return film_fused<T, 7>(c, f.H, f.w1f, hde, parts(pr.A, pr.nb, pr.C, pr.F), K_FILM_ROWS_INV_UPD);
 }
 
 template <typename T>
@@ -1137,10 +1162,10 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   law.jc0 = c->jc0;
   law.has_jc = c->has_jc_map ? 1 : 0;
   const long long n = c->nnode;
-  const int nbs = (int)((n + kStencilThreads * kStencilNpt - 1) / (kStencilThreads * kStencilNpt));   // stencil blocks
+  const int nbs = film_stencil_blocks(c);
   {
-    ProfScope ps(c, K_FILM_STENCIL);
-    hipLaunchKernelGGL((film_stencil<T>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat, c->d_flags,
+    ProfLaunch ps(c, K_FILM_STENCIL);
+    MAG_TIMED_LAUNCH(ps, (film_stencil<T>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat, c->d_flags,
                        reinterpret_cast<const T *>(c->d_jc), f.H, G, law, hde, c->warm_valid ? 1 : 0,
                        film_regions<T>(c).X);
   }
@@ -1379,7 +1404,7 @@ int film_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_mat, n));
   c->npart = (int)((n + 255) / 256 + 2 * c->n[1] + 16);   // 256-node blocks, or up to 5 regions of row blocks
   MAG_HIP(c, hipMalloc(&c->d_part, (size_t)c->npart * sizeof(double)));
-  MAG_HIP(c, hipMalloc(&c->d_w, 2 * n * ts));
+  MAG_HIP(c, hipMalloc(&c->d_w, 3 * n * ts));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
   MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
   // |k|^2 per axis: k = 2 pi fftfreq(n, d)
@@ -1435,6 +1460,9 @@ static int film_weights_t(mag_ctx *c, double *tmp) {
     ProfScope ps(c, K_MISC);
     hipLaunchKernelGGL((weights_k<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, tmp + n,
                        w + which * n, c->d_flags, which, n);
+    if (which == 0)
+      hipLaunchKernelGGL((weights_k<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, tmp + n,
+                         w + 2 * n, c->d_flags, 1, n);
   }
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;

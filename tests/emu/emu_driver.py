@@ -67,7 +67,8 @@ def main(path, which):
     if which in ("film", "all"):
         cases += [("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2),
                   ("film", film_case(16, 32, L=(1.0, 2.0), kind="ring", rho_out=20.0), 1, 1),
-                  ("film", film_case(128, 64, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2)]
+                  ("film", film_case(128, 64, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2),
+                  ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 1, 3)]
     for name, case, prec, fixed in cases:
         h, keep = setup(L, case, prec, fixed=fixed)
         rc, it, out = run_rhs(L, h, case["state"], 0.2)
