@@ -122,9 +122,6 @@ struct mag_ctx {
   double *d_red = nullptr;        // reduction scratch for step control
   int nred = 0;
 
-  // adjoint scratch
-  void *d_adj = nullptr;
-  long long adj_bytes = 0;
 
   // instrumentation
   bool debug_sync = false;        // MAG_DEBUG_SYNC=1: synchronise and check after every launch

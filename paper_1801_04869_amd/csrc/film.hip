@@ -819,31 +819,31 @@ __global__ void __launch_bounds__(256) sum_blocks(const double *__restrict__ x, 
 //   de/dj_own = rho (1 + (n-1) j_own^2 / s^2),   de/doth = rho (n-1) j_own oth / s^2,
 //   de/djc_edge = -n e / jc_edge   (superconducting edges; rho_out elsewhere).
 // Stored per edge (double): ebar de/dj_own, ebar de/doth, ebar de/djc.
-template <typename T>
-__device__ __forceinline__ void film_edge_vjp(const double *__restrict__ g, const uint8_t *__restrict__ mat,
-                                              const T *__restrict__ jc, const FilmGeom &G, const FilmLaw &law,
-                                              int p, int q, int orient, double ebar, double *own, double *oth_bar,
+// gv(pp, qq), mv(pp, qq), jv(pp, qq): g at node (pp, qq), material and jc of
+// cell (pp, qq); coordinates not wrapped.
+template <typename T, typename GV, typename MV, typename JV>
+__device__ __forceinline__ void film_edge_vjp(GV gv, MV mv, JV jv, const FilmGeom &G, const FilmLaw &law, int p,
+                                              int q, int orient, double ebar, double *own, double *oth_bar,
                                               double *jc_bar) {
-  const int nx = G.nx, ny = G.ny;
-  auto gv = [&](int pp, int qq) { return g[(long long)wrap(qq, ny) * nx + wrap(pp, nx)]; };
   auto jxv = [&](int pp, int qq) { return (gv(pp, qq + 1) - gv(pp, qq)) * G.idy; };
   auto jyv = [&](int pp, int qq) { return -(gv(pp + 1, qq) - gv(pp, qq)) * G.idx; };
   double jo, oth;
-  const long long c0 = (long long)wrap(q, ny) * nx + wrap(p, nx);
-  long long c1;
+  int p1, q1;   // the other cell of the edge
   if (orient == 0) {
     jo = jxv(p, q);
     oth = 0.25 * (jyv(p - 1, q) + jyv(p, q) + jyv(p - 1, q + 1) + jyv(p, q + 1));
-    c1 = (long long)wrap(q, ny) * nx + wrap(p - 1, nx);
+    p1 = p - 1;
+    q1 = q;
   } else {
     jo = jyv(p, q);
     oth = 0.25 * (jxv(p, q - 1) + jxv(p, q) + jxv(p + 1, q - 1) + jxv(p + 1, q));
-    c1 = (long long)wrap(q - 1, ny) * nx + wrap(p, nx);
+    p1 = p;
+    q1 = q - 1;
   }
-  if (mat[c0] == 1 && mat[c1] == 1) {
+  if (mv(p, q) == 1 && mv(p1, q1) == 1) {
     const T jt = (T)jo, ot = (T)oth;
     const T s = sqrt(jt * jt + ot * ot);
-    const T jce = law.has_jc ? (T)0.5 * (jc[c0] + jc[c1]) : (T)law.jc0;
+    const T jce = law.has_jc ? (T)0.5 * (jv(p, q) + jv(p1, q1)) : (T)law.jc0;
     const T nm1 = (T)law.nm1;
     T a, b;
     if (s > (T)0) {
@@ -866,68 +866,80 @@ __device__ __forceinline__ void film_edge_vjp(const double *__restrict__ g, cons
   }
 }
 
-// Per node (p, q): the edge terms of its x-edge and y-edge, written to the
-// planes E[0..3] (own_x, oth_x, own_y, oth_y) and, when the jc map is wanted,
-// E[4..5] (jc_x, jc_y); stored in the compute precision.
-template <typename T>
-__global__ void __launch_bounds__(256) film_vjp_edges(const double *__restrict__ g, const uint8_t *__restrict__ mat,
-                                                      const uint8_t *__restrict__ flags, const T *__restrict__ jc,
-                                                      const T *__restrict__ mu, FilmGeom G, FilmLaw law,
-                                                      T *__restrict__ E, int want_jc,
-                                                      const IterState *__restrict__ it) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long n = (long long)G.nx * G.ny;
-  if (i >= n) return;
-  const int p = (int)(i % G.nx), q = (int)(i / G.nx);
-  const double C = it->C;
-  auto hb = [&](int pp, int qq) {
-    const long long k = (long long)wrap(qq, G.ny) * G.nx + wrap(pp, G.nx);
-    return (flags[k] & 1) ? (double)mu[k] - C : 0.0;
-  };
-  const double h0 = hb(p, q);
-  // dh(p,q) = -[(e_y(p,q) - e_y(p-1,q))/dx - (e_x(p,q) - e_x(p,q-1))/dy]
-  const double ebx = (h0 - hb(p, q + 1)) * G.idy;
-  const double eby = (hb(p + 1, q) - h0) * G.idx;
-  double o, b, cj;
-  film_edge_vjp<T>(g, mat, jc, G, law, p, q, 0, ebx, &o, &b, &cj);
-  E[i] = (T)o;
-  E[i + n] = (T)b;
-  if (want_jc) E[i + 4 * n] = (T)cj;
-  film_edge_vjp<T>(g, mat, jc, G, law, p, q, 1, eby, &o, &b, &cj);
-  E[i + 2 * n] = (T)o;
-  E[i + 3 * n] = (T)b;
-  if (want_jc) E[i + 5 * n] = (T)cj;
-}
+// Fused stencil transpose on a kVjpTile^2 tile of nodes: g (two-node halo)
+// and the film-node cotangent hbar = mu - C (one node beyond the far sides)
+// are staged in LDS; the edge terms of the x- and y-edge of every node of the
+// tile and a one-node halo are computed into LDS (edges whose cotangent is 0,
+// all of them away from the film, are skipped); then, per node, the
+// edge-current cotangents (own part plus a quarter of the neighbour-mean parts
+// of the four other-orientation edges that average this edge into their |j|),
+// g_bar by the transpose of eq. (2), and the cell jc_bar from its four edges
+// (edge jc = mean of two cells).
+constexpr int kVjpTile = 16;
 
-// Per node: the edge-current cotangents (own part plus a quarter of the
-// neighbour-mean parts of the four other-orientation edges that average this
-// edge into their |j|), then g_bar by the transpose of eq. (2), and the cell
-// jc_bar from its four edges (edge jc = mean of two cells).
 template <typename T>
-__global__ void __launch_bounds__(256) film_vjp_gather(const T *__restrict__ E, double *__restrict__ gbar,
-                                                       double *__restrict__ jcbar, double jc0, FilmGeom G) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long n = (long long)G.nx * G.ny;
-  if (i >= n) return;
-  const int p = (int)(i % G.nx), q = (int)(i / G.nx);
-  auto at = [&](int pp, int qq) { return (long long)wrap(qq, G.ny) * G.nx + wrap(pp, G.nx); };
-  const T *own_x = E, *oth_x = E + n, *own_y = E + 2 * n, *oth_y = E + 3 * n;
+__global__ void __launch_bounds__(kVjpTile * kVjpTile)
+    film_vjp_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+                     const uint8_t *__restrict__ flags, const T *__restrict__ jc, const T *__restrict__ mu,
+                     FilmGeom G, FilmLaw law, double *__restrict__ gbar, double *__restrict__ jcbar, double jc0,
+                     const IterState *__restrict__ it) {
+  constexpr int B = kVjpTile, NT = B * B;
+  constexpr int GW = B + 4;   // g on [p0-2, p0+B+2)
+  constexpr int HW = B + 3;   // hbar on [p0-1, p0+B+2)
+  constexpr int EW = B + 2;   // edge terms on [p0-1, p0+B+1)
+  __shared__ double gs[GW * GW];
+  __shared__ double hs[HW * HW];
+  __shared__ T es[6][EW * EW];   // own_x, oth_x, own_y, oth_y, jc_x, jc_y
+  const int p0 = blockIdx.x * B, q0 = blockIdx.y * B;
+  const double C = it->C;
+  for (int k = threadIdx.x; k < GW * GW; k += NT) {
+    const int a = k % GW, b = k / GW;
+    gs[k] = g[(long long)wrap(q0 - 2 + b, G.ny) * G.nx + wrap(p0 - 2 + a, G.nx)];
+  }
+  for (int k = threadIdx.x; k < HW * HW; k += NT) {
+    const int a = k % HW, b = k / HW;
+    const long long idx = (long long)wrap(q0 - 1 + b, G.ny) * G.nx + wrap(p0 - 1 + a, G.nx);
+    hs[k] = (flags[idx] & 1) ? (double)mu[idx] - C : 0.0;
+  }
+  __syncthreads();
+  // material and jc are read from memory only for edges next to the film
+  auto gv = [&](int pp, int qq) { return gs[(qq - q0 + 2) * GW + (pp - p0 + 2)]; };
+  auto cell = [&](int pp, int qq) { return (long long)wrap(qq, G.ny) * G.nx + wrap(pp, G.nx); };
+  auto mv = [&](int pp, int qq) { return mat[cell(pp, qq)]; };
+  auto jv = [&](int pp, int qq) { return jc[cell(pp, qq)]; };
+  auto hb = [&](int pp, int qq) { return hs[(qq - q0 + 1) * HW + (pp - p0 + 1)]; };
+  for (int k = threadIdx.x; k < EW * EW; k += NT) {
+    const int p = p0 - 1 + k % EW, q = q0 - 1 + k / EW;
+    // dh(p,q) = -[(e_y(p,q) - e_y(p-1,q))/dx - (e_x(p,q) - e_x(p,q-1))/dy]
+    const double h0 = hb(p, q);
+    const double ebx = (h0 - hb(p, q + 1)) * G.idy;
+    const double eby = (hb(p + 1, q) - h0) * G.idx;
+    double o = 0.0, b = 0.0, cj = 0.0;
+    if (ebx != 0.0) film_edge_vjp<T>(gv, mv, jv, G, law, p, q, 0, ebx, &o, &b, &cj);
+    es[0][k] = (T)o;
+    es[1][k] = (T)b;
+    es[4][k] = (T)cj;
+    o = b = cj = 0.0;
+    if (eby != 0.0) film_edge_vjp<T>(gv, mv, jv, G, law, p, q, 1, eby, &o, &b, &cj);
+    es[2][k] = (T)o;
+    es[3][k] = (T)b;
+    es[5][k] = (T)cj;
+  }
+  __syncthreads();
+  const int p = p0 + threadIdx.x % B, q = q0 + threadIdx.x / B;
+  auto E = [&](int pl, int pp, int qq) { return (double)es[pl][(qq - q0 + 1) * EW + (pp - p0 + 1)]; };
   // x-edge (pp, qq) is averaged into the y-edges (pp, qq), (pp, qq+1), (pp-1, qq), (pp-1, qq+1)
   auto jbx = [&](int pp, int qq) {
-    return (double)own_x[at(pp, qq)] + 0.25 * ((double)oth_y[at(pp, qq)] + (double)oth_y[at(pp, qq + 1)] +
-                                               (double)oth_y[at(pp - 1, qq)] + (double)oth_y[at(pp - 1, qq + 1)]);
+    return E(0, pp, qq) + 0.25 * (E(3, pp, qq) + E(3, pp, qq + 1) + E(3, pp - 1, qq) + E(3, pp - 1, qq + 1));
   };
   // y-edge (pp, qq) is averaged into the x-edges (pp, qq), (pp+1, qq), (pp, qq-1), (pp+1, qq-1)
   auto jby = [&](int pp, int qq) {
-    return (double)own_y[at(pp, qq)] + 0.25 * ((double)oth_x[at(pp, qq)] + (double)oth_x[at(pp + 1, qq)] +
-                                               (double)oth_x[at(pp, qq - 1)] + (double)oth_x[at(pp + 1, qq - 1)]);
+    return E(2, pp, qq) + 0.25 * (E(1, pp, qq) + E(1, pp + 1, qq) + E(1, pp, qq - 1) + E(1, pp + 1, qq - 1));
   };
+  const long long i = (long long)q * G.nx + p;
   // j_x(p,q) = (g(p,q+1) - g(p,q))/dy,  j_y(p,q) = -(g(p+1,q) - g(p,q))/dx
   gbar[i] = (jbx(p, q - 1) - jbx(p, q)) * G.idy + (jby(p, q) - jby(p - 1, q)) * G.idx;
-  if (jcbar) {
-    const T *jcx = E + 4 * n, *jcy = E + 5 * n;
-    jcbar[i] = jc0 * 0.5 * ((double)jcx[i] + (double)jcx[at(p + 1, q)] + (double)jcy[i] + (double)jcy[at(p, q + 1)]);
-  }
+  if (jcbar) jcbar[i] = jc0 * 0.5 * (E(4, p, q) + E(4, p + 1, q) + E(5, p, q) + E(5, p, q + 1));
 }
 
 }  // namespace
@@ -1296,15 +1308,6 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   const FilmPtrs<T> f = fptrs<T>(c);
   const long long n = c->nnode;
   const int nb = (int)((n + 255) / 256);
-  const long long need = 6 * n * (long long)sizeof(T);
-  if (c->adj_bytes < need) {
-    if (c->d_adj) (void)hipFree(c->d_adj);
-    c->d_adj = nullptr;
-    c->adj_bytes = 0;
-    MAG_HIP(c, hipMalloc(&c->d_adj, need));
-    c->adj_bytes = need;
-  }
-  T *E = reinterpret_cast<T *>(c->d_adj);
   T *Mu = f.G;   // the forward's G is scratch between calls
   IterState is{};
   is.fixed = c->fixed_iters;
@@ -1378,10 +1381,10 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   law.jc0 = c->jc0;
   law.has_jc = c->has_jc_map ? 1 : 0;
   {
-    ProfScope ps(c, K_VJP);
-    hipLaunchKernelGGL((film_vjp_edges<T>), dim3(nb), dim3(256), 0, c->stream, state, c->d_mat, c->d_flags,
-                       reinterpret_cast<const T *>(c->d_jc), Mu, G, law, E, jcbar ? 1 : 0, c->d_it);
-    hipLaunchKernelGGL((film_vjp_gather<T>), dim3(nb), dim3(256), 0, c->stream, E, gbar, jcbar, c->jc0, G);
+    ProfLaunch ps(c, K_VJP);
+    MAG_TIMED_LAUNCH(ps, (film_vjp_stencil<T>), dim3(G.nx / kVjpTile, G.ny / kVjpTile), dim3(kVjpTile * kVjpTile),
+                     0, c->stream, state, c->d_mat, c->d_flags, reinterpret_cast<const T *>(c->d_jc), Mu, G, law,
+                     gbar, jcbar, c->jc0, c->d_it);
   }
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
