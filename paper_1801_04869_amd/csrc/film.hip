@@ -144,7 +144,8 @@ struct FilmRowShape {
   // Waves per SIMD that a square grid (ny = 2M rows) needs resident for its
   // row blocks to run in one round on 256 CUs, capped by what LDS (160 KB
   // per CU) admits: the register budget handed to the compiler.
-  static constexpr int BLOCKS_LDS = (160 * 1024) / (LDS_T * (int)sizeof(T) + 1024);
+  static constexpr int TW_BYTES = sizeof(T) == 4 ? 2 * M * 2 * (int)sizeof(T) : 0;   // see row_twiddles
+  static constexpr int BLOCKS_LDS = (160 * 1024) / (LDS_T * (int)sizeof(T) + TW_BYTES + 1024);
   static constexpr int BLOCKS_SQ = ((2 * M + P - 1) / P + 255) / 256;
   static constexpr int BLOCKS_CU = BLOCKS_SQ < BLOCKS_LDS ? BLOCKS_SQ : BLOCKS_LDS;
   static constexpr int WAVES_EU_RAW = BLOCKS_CU * ((THREADS + 63) / 64) / 4;
@@ -187,6 +188,23 @@ struct FilmColShape {
   static_assert(LDS_T * sizeof(T) <= 150 * 1024, "column block LDS too large");
 };
 
+// FP32 row passes read the twiddle tables of the row transform (length M
+// and the real-to-complex step) from LDS: the block copies them at its start,
+// with its other loads, and every first use follows a barrier.  FP64 reads
+// them from memory (their LDS would cost a resident block per CU).
+template <typename T, int M, int THREADS>
+__device__ __forceinline__ void row_twiddles(const cx<T> *__restrict__ &twM, const cx<T> *__restrict__ &twN) {
+  if constexpr (sizeof(T) == 4) {
+    __shared__ __align__(16) cx<T> lm[M], ln[M];
+    for (int i = threadIdx.x; i < M; i += THREADS) {
+      lm[i] = twM[i];
+      ln[i] = twN[i];
+    }
+    twM = lm;
+    twN = ln;
+  }
+}
+
 // Row transforms (real-to-complex along x, output transposed).
 // MODE 0: H rows (apply shift A on free space, write back, transform H - dh_e).
 // MODE 1: G rows (gdot = G - C, per-block sums of |gdot| on free space,
@@ -205,6 +223,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  row_twiddles<T, M, RS::THREADS>(twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
@@ -341,6 +360,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[3 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  row_twiddles<T, M, RS::THREADS>(twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
@@ -474,6 +494,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  row_twiddles<T, M, RS::THREADS>(twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
@@ -610,6 +631,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  row_twiddles<T, M, RS::THREADS>(twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
