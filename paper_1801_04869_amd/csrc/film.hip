@@ -142,12 +142,15 @@ struct FilmRowShape {
   static constexpr int LDS_T = XCH > STG ? XCH : STG;
   static constexpr int THREADS = P * TT;
   // Waves per SIMD that a square grid (ny = 2M rows) needs resident for its
-  // row blocks to run in one round on 256 CUs, capped by what LDS (160 KB
-  // per CU) admits: the register budget handed to the compiler.
+  // row blocks to run in the fewest rounds on 256 CUs that LDS (160 KB per
+  // CU) allows, spread evenly over those rounds: the register budget handed
+  // to the compiler.
   static constexpr int TW_BYTES = sizeof(T) == 4 ? 2 * M * 2 * (int)sizeof(T) : 0;   // see row_twiddles
-  static constexpr int BLOCKS_LDS = (160 * 1024) / (LDS_T * (int)sizeof(T) + TW_BYTES + 1024);
+  static constexpr int BLOCKS_LDS_RAW = (160 * 1024) / (LDS_T * (int)sizeof(T) + TW_BYTES + 1024);
+  static constexpr int BLOCKS_LDS = BLOCKS_LDS_RAW < 1 ? 1 : BLOCKS_LDS_RAW;
   static constexpr int BLOCKS_SQ = ((2 * M + P - 1) / P + 255) / 256;
-  static constexpr int BLOCKS_CU = BLOCKS_SQ < BLOCKS_LDS ? BLOCKS_SQ : BLOCKS_LDS;
+  static constexpr int ROUNDS = (BLOCKS_SQ + BLOCKS_LDS - 1) / BLOCKS_LDS;
+  static constexpr int BLOCKS_CU = (BLOCKS_SQ + ROUNDS - 1) / ROUNDS;
   static constexpr int WAVES_EU_RAW = BLOCKS_CU * ((THREADS + 63) / 64) / 4;
   static constexpr int WAVES_EU = WAVES_EU_RAW < 1 ? 1 : (WAVES_EU_RAW > 8 ? 8 : WAVES_EU_RAW);
   static_assert(THREADS <= 1024, "row block too large");
@@ -188,17 +191,93 @@ struct FilmColShape {
   static_assert(LDS_T * sizeof(T) <= 150 * 1024, "column block LDS too large");
 };
 
+// Tile traffic of a row pass: entries (k, r), k = 0..M, r = 0..P-1, of the
+// transposed spectrum S[k][q0 + r].  tile_fetch issues all of a work-item's
+// loads into registers at once (one round trip to memory, not one per loop
+// trip); tile_put stores them to the LDS tile [M+1][SP]; tile_store writes
+// the tile back.  Rows past ny read entry 0 and are dropped.
+template <typename T, int M, int P, int THREADS>
+struct TileRegs {
+  static constexpr int NE = (M + 1) * P, NU = (NE + THREADS - 1) / THREADS;
+  cx<T> t[NU];
+};
+
+template <typename T, int M, int P, int THREADS>
+__device__ __forceinline__ void tile_fetch(TileRegs<T, M, P, THREADS> &tr, const cx<T> *__restrict__ S, int ny,
+                                           int q0) {
+  using TR = TileRegs<T, M, P, THREADS>;
+#pragma unroll
+  for (int u = 0; u < TR::NU; ++u) {
+    const int idx = threadIdx.x + u * THREADS;
+    const int k = idx / P, r = idx % P;
+    const bool ok = idx < TR::NE && q0 + r < ny;
+    const cx<T> v = S[ok ? (long long)k * ny + q0 + r : 0];
+    tr.t[u] = ok ? v : cx<T>{(T)0, (T)0};
+  }
+}
+
+template <typename T, int M, int P, int SP, int THREADS>
+__device__ __forceinline__ void tile_put(cx<T> *tile, const TileRegs<T, M, P, THREADS> &tr) {
+  using TR = TileRegs<T, M, P, THREADS>;
+#pragma unroll
+  for (int u = 0; u < TR::NU; ++u) {
+    const int idx = threadIdx.x + u * THREADS;
+    if (idx < TR::NE) tile[(idx / P) * SP + idx % P] = tr.t[u];
+  }
+}
+
+template <typename T, int M, int P, int SP, int THREADS>
+__device__ __forceinline__ void tile_store(const cx<T> *tile, cx<T> *__restrict__ S, int ny, int q0) {
+  constexpr int NE = (M + 1) * P, NU = (NE + THREADS - 1) / THREADS;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int idx = threadIdx.x + u * THREADS;
+    const int k = idx / P, r = idx % P;
+    if (idx < NE && q0 + r < ny) S[(long long)k * ny + q0 + r] = tile[k * SP + r];
+  }
+}
+
 // FP32 row passes read the twiddle tables of the row transform (length M
-// and the real-to-complex step) from LDS: the block copies them at its start,
-// with its other loads, and every first use follows a barrier.  FP64 reads
-// them from memory (their LDS would cost a resident block per CU).
+// and the real-to-complex step) from LDS: the block fetches them with its
+// other loads (row_tw_fetch), stores them (row_tw_put, which points twM and
+// twN at the copies) and every first use follows a barrier.  FP64 reads them
+// from memory (their LDS would cost a resident block per CU).
 template <typename T, int M, int THREADS>
-__device__ __forceinline__ void row_twiddles(const cx<T> *__restrict__ &twM, const cx<T> *__restrict__ &twN) {
-  if constexpr (sizeof(T) == 4) {
+struct RowTw {
+  static constexpr bool ON = sizeof(T) == 4;
+  static constexpr int NU = (M + THREADS - 1) / THREADS;
+  cx<T> m[ON ? NU : 1], n[ON ? NU : 1];
+};
+
+template <typename T, int M, int THREADS>
+__device__ __forceinline__ void row_tw_fetch(RowTw<T, M, THREADS> &rt, const cx<T> *__restrict__ twM,
+                                             const cx<T> *__restrict__ twN) {
+  using RT = RowTw<T, M, THREADS>;
+  if constexpr (RT::ON) {
+#pragma unroll
+    for (int u = 0; u < RT::NU; ++u) {
+      const int i = threadIdx.x + u * THREADS;
+      if (i < M) {
+        rt.m[u] = twM[i];
+        rt.n[u] = twN[i];
+      }
+    }
+  }
+}
+
+template <typename T, int M, int THREADS>
+__device__ __forceinline__ void row_tw_put(const RowTw<T, M, THREADS> &rt, const cx<T> *__restrict__ &twM,
+                                           const cx<T> *__restrict__ &twN) {
+  using RT = RowTw<T, M, THREADS>;
+  if constexpr (RT::ON) {
     __shared__ __align__(16) cx<T> lm[M], ln[M];
-    for (int i = threadIdx.x; i < M; i += THREADS) {
-      lm[i] = twM[i];
-      ln[i] = twN[i];
+#pragma unroll
+    for (int u = 0; u < RT::NU; ++u) {
+      const int i = threadIdx.x + u * THREADS;
+      if (i < M) {
+        lm[i] = rt.m[u];
+        ln[i] = rt.n[u];
+      }
     }
     twM = lm;
     twN = ln;
@@ -223,12 +302,30 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  row_twiddles<T, M, RS::THREADS>(twM, twN);
+  RowTw<T, M, RS::THREADS> rtw;
+  row_tw_fetch(rtw, twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
+  // MODE 0: this thread's nodes 2m, 2m+1 (m = j + rho TT) of H, their flags
+  // and w1, all loaded before any is used (a row past ny reads row 0 and is
+  // not used).
+  T h0[RMAX][2], w0[RMAX][2];
+  uint16_t f0[RMAX];
+  if constexpr (MODE == 0) {
+    const T *wsrc = w1 ? w1 : X;   // without w1 the values read are not used
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const long long o = ro + 2 * (j + rho * TT);
+      h0[rho][0] = X[o];
+      h0[rho][1] = X[o + 1];
+      f0[rho] = *reinterpret_cast<const uint16_t *>(flags + o);
+      w0[rho][0] = wsrc[o];
+      w0[rho][1] = wsrc[o + 1];
+    }
+  }
   // MODE 0: the shift A of (10) from the previous update's sums (or the
   // stencil's, already reduced into it->A); MODE 1: C = free-space mean of G.
   double shift = 0.0;
@@ -252,15 +349,15 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       const int p = 2 * (j + rho * TT) + e;
       if (!active) continue;
       if constexpr (MODE == 0) {
-        T h = X[ro + p];
-        const bool film = flags[ro + p] & 1;
+        T h = h0[rho][e];
+        const bool film = (f0[rho] >> (8 * e)) & 1;
         if (!film) {
           h = (T)((double)h - shift);
           X[ro + p] = h;
         }
         val[e] = (T)((double)h - hde);
         if (w1) {
-          const double t = (double)w1[ro + p] * ((double)h - hde);
+          const double t = (double)w0[rho][e] * ((double)h - hde);
           acc += t;
           if (film) acc_film += t;
         }
@@ -280,6 +377,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     }
     v[rho] = {val[0], val[1]};
   }
+  row_tw_put(rtw, twM, twN);   // first read after the transform's entry barrier
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
   pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
   // Half spectrum of the real row from the packed transform Z:
@@ -306,10 +404,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
   if (j == 0) tile[M * SP + pr] = xm;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
-    const int k = idx / P, r = idx % P;
-    if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
-  }
+  tile_store<T, M, P, SP, RS::THREADS>(tile, S, G.ny, q0);
   if constexpr (MODE == 1) {
     const double sblk = block_total<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) pp.out[blk] = sblk;
@@ -360,17 +455,17 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[3 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  row_twiddles<T, M, RS::THREADS>(twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
+  // tile, twiddles and partial sums fetched together, then stored
   cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
-  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
-    const int k = idx / P, r = idx % P;
-    tile[k * SP + r] = q0 + r < G.ny ? S[(long long)k * G.ny + q0 + r] : cx<T>{(T)0, (T)0};
-  }
+  TileRegs<T, M, P, RS::THREADS> tr;
+  tile_fetch(tr, S, G.ny, q0);
+  RowTw<T, M, RS::THREADS> rtw;
+  row_tw_fetch(rtw, twM, twN);
   double c_new = 0.0, c_old = 0.0, a_z = 0.0;
   if constexpr (MODE == 8) {
     c_new = pp.c_new * parts_sum(pp.in_new, pp.nin);
@@ -379,6 +474,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   } else {
     a_z = parts_sum(pp.in_a, pp.nin) * it->inv_nout;
   }
+  tile_put<T, M, P, SP, RS::THREADS>(tile, tr);
+  row_tw_put(rtw, twM, twN);
   __syncthreads();
   cx<T> v[RMAX];
 #pragma unroll
@@ -446,10 +543,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
   if (j == 0) tile[M * SP + pr] = xm;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
-    const int k = idx / P, r = idx % P;
-    if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
-  }
+  tile_store<T, M, P, SP, RS::THREADS>(tile, S, G.ny, q0);
   constexpr int NW = RS::THREADS / 64;
   const double s1 = block_total<RS::THREADS>(acc, red);
   if (threadIdx.x == 0) pp.out[blk] = s1;
@@ -494,27 +588,21 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  row_twiddles<T, M, RS::THREADS>(twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
-  // The weights of this thread's nodes 2m, 2m+1 (m = j + rho TT), NaN on
-  // film nodes (so they carry the free-space flag too), loaded first so that
-  // their latency overlaps the tile load and the complex-to-real transform.
-  T wpre[RMAX][2];
-#pragma unroll
-  for (int rho = 0; rho < RMAX; ++rho) {
-    const long long o = ro + 2 * (j + rho * TT);
-    wpre[rho][0] = active ? w[o] : (T)0;
-    wpre[rho][1] = active ? w[o + 1] : (T)0;
-  }
+  // Loads in the order they are needed (memory returns them in order): the
+  // tile, the twiddles, the partial sums, then the weights of this thread's
+  // nodes 2m, 2m+1 (m = j + rho TT; NaN on film nodes, so they carry the
+  // free-space flag too; a row past ny reads row 0 and is not used), which
+  // stay in flight while the tile is stored to LDS and transformed.
   cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
-  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
-    const int k = idx / P, r = idx % P;
-    tile[k * SP + r] = q0 + r < G.ny ? S[(long long)k * G.ny + q0 + r] : cx<T>{(T)0, (T)0};
-  }
+  TileRegs<T, M, P, RS::THREADS> tr;
+  tile_fetch(tr, S, G.ny, q0);
+  RowTw<T, M, RS::THREADS> rtw;
+  row_tw_fetch(rtw, twM, twN);
   double cst;
   if constexpr (MODE == 6) {
     cst = parts_sum(pp.in, pp.nin) * it->inv_nout;   // C
@@ -522,6 +610,15 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   } else {
     cst = -lam * parts_sum(pp.in, pp.nin) * it->inv_nout;   // A
   }
+  T wpre[RMAX][2];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const long long o = ro + 2 * (j + rho * TT);
+    wpre[rho][0] = w[o];
+    wpre[rho][1] = w[o + 1];
+  }
+  tile_put<T, M, P, SP, RS::THREADS>(tile, tr);
+  row_tw_put(rtw, twM, twN);
   __syncthreads();
   cx<T> v[RMAX];
 #pragma unroll
@@ -594,10 +691,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
   if (j == 0) tile[M * SP + pr] = xm;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
-    const int k = idx / P, r = idx % P;
-    if (q0 + r < G.ny) S[(long long)k * G.ny + q0 + r] = tile[k * SP + r];
-  }
+  tile_store<T, M, P, SP, RS::THREADS>(tile, S, G.ny, q0);
   const double s1 = block_total<RS::THREADS>(acc, red);
   if constexpr (MODE == 6) {
     if (threadIdx.x == 0) pp.out[blk] = s1;
@@ -631,7 +725,6 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   __shared__ __align__(16) T lds[RS::LDS_T];
   __shared__ double red[2 * (RS::THREADS / 64)];
   const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
-  row_twiddles<T, M, RS::THREADS>(twM, twN);
   const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
   const int q0 = blk * P;
   const int q = q0 + pr;
@@ -640,9 +733,13 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   const double cmean = MODE == 4 ? it->C : 0.0;
   double acc2 = 0.0;
   cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
-  for (int idx = threadIdx.x; idx < (M + 1) * P; idx += RS::THREADS) {
-    const int k = idx / P, r = idx % P;
-    tile[k * SP + r] = q0 + r < G.ny ? S[(long long)k * G.ny + q0 + r] : cx<T>{(T)0, (T)0};
+  {
+    TileRegs<T, M, P, RS::THREADS> tr;
+    tile_fetch(tr, S, G.ny, q0);
+    RowTw<T, M, RS::THREADS> rtw;
+    row_tw_fetch(rtw, twM, twN);
+    tile_put<T, M, P, SP, RS::THREADS>(tile, tr);
+    row_tw_put(rtw, twM, twN);
   }
   __syncthreads();
   // Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]); the inverse

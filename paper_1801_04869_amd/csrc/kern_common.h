@@ -89,12 +89,21 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum of part[0..n) computed by one wavefront in a fixed order (lane l adds
-// part[l], part[l+64], ... then the butterfly): every wavefront of every block
+// part[l], part[l+64], ... in index order, then the butterfly): every wavefront of every block
 // that calls it on the same data gets the same bits, with no barrier.
 __device__ __forceinline__ double parts_sum(const double *__restrict__ part, int n) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int i = lane; i < n; i += 64) s += part[i];
+  int i = lane;
+  // eight loads in flight per lane, added in index order
+  for (; i + 7 * 64 < n; i += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[i + u * 64];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; i < n; i += 64) s += part[i];
   return wave_sum(s);
 }
 
