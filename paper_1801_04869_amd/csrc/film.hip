@@ -94,13 +94,24 @@ __global__ void __launch_bounds__(kStencilThreads) film_stencil(const double *__
   const long long n = (long long)G.nx * G.ny;
   const long long i0 = (long long)blockIdx.x * (kStencilThreads * kStencilNpt) + threadIdx.x;
   double acc = 0.0;
+  // the flags (and warm starts) of all of this thread's nodes first, in one
+  // batch: free-space nodes then need no further load
+  uint8_t fl[kStencilNpt];
+  T hw[kStencilNpt];
+#pragma unroll
+  for (int k = 0; k < kStencilNpt; ++k) {
+    const long long i = i0 + (long long)k * kStencilThreads;
+    const long long ic = i < n ? i : 0;
+    fl[k] = flags[ic];
+    hw[k] = warm ? H[ic] : (T)0;
+  }
 #pragma unroll 1
   for (int k = 0; k < kStencilNpt; ++k) {
     const long long i = i0 + (long long)k * kStencilThreads;
     if (i >= n) break;
     const int p = (int)(i % G.nx), q = (int)(i / G.nx);
     T h;
-    if (flags[i] & 1) {
+    if (fl[k] & 1) {
       const T exq = film_edge_e<T>(g, mat, jc, G, law, p, q, 0);
       const T exm = film_edge_e<T>(g, mat, jc, G, law, p, q - 1, 0);
       const T eyp = film_edge_e<T>(g, mat, jc, G, law, p, q, 1);
@@ -109,7 +120,7 @@ __global__ void __launch_bounds__(kStencilThreads) film_stencil(const double *__
       h = (T)(-curl);
       H[i] = h;
     } else if (warm) {
-      h = H[i];
+      h = hw[k];
     } else {
       h = (T)hde;
       H[i] = h;
@@ -1011,15 +1022,29 @@ __global__ void __launch_bounds__(kVjpTile * kVjpTile)
   __shared__ T es[6][EW * EW];   // own_x, oth_x, own_y, oth_y, jc_x, jc_y
   const int p0 = blockIdx.x * B, q0 = blockIdx.y * B;
   const double C = it->C;
-  for (int k = threadIdx.x; k < GW * GW; k += NT) {
-    const int a = k % GW, b = k / GW;
-    gs[k] = g[(long long)wrap(q0 - 2 + b, G.ny) * G.nx + wrap(p0 - 2 + a, G.nx)];
+  // staging loads issued together (one round trip), then stored
+  constexpr int NG = (GW * GW + NT - 1) / NT, NH = (HW * HW + NT - 1) / NT;
+  double gl[NG];
+  uint8_t fh[NH];
+  T muh[NH];
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    const int k = threadIdx.x + u * NT, kc = k < GW * GW ? k : 0;
+    gl[u] = g[(long long)wrap(q0 - 2 + kc / GW, G.ny) * G.nx + wrap(p0 - 2 + kc % GW, G.nx)];
   }
-  for (int k = threadIdx.x; k < HW * HW; k += NT) {
-    const int a = k % HW, b = k / HW;
-    const long long idx = (long long)wrap(q0 - 1 + b, G.ny) * G.nx + wrap(p0 - 1 + a, G.nx);
-    hs[k] = (flags[idx] & 1) ? (double)mu[idx] - C : 0.0;
+#pragma unroll
+  for (int u = 0; u < NH; ++u) {
+    const int k = threadIdx.x + u * NT, kc = k < HW * HW ? k : 0;
+    const long long idx = (long long)wrap(q0 - 1 + kc / HW, G.ny) * G.nx + wrap(p0 - 1 + kc % HW, G.nx);
+    fh[u] = flags[idx];
+    muh[u] = mu[idx];
   }
+#pragma unroll
+  for (int u = 0; u < NG; ++u)
+    if (threadIdx.x + u * NT < GW * GW) gs[threadIdx.x + u * NT] = gl[u];
+#pragma unroll
+  for (int u = 0; u < NH; ++u)
+    if (threadIdx.x + u * NT < HW * HW) hs[threadIdx.x + u * NT] = (fh[u] & 1) ? (double)muh[u] - C : 0.0;
   __syncthreads();
   // material and jc are read from memory only for edges next to the film
   auto gv = [&](int pp, int qq) { return gs[(qq - q0 + 2) * GW + (pp - p0 + 2)]; };
