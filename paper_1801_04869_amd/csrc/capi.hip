@@ -169,7 +169,16 @@ namespace {
 
 __device__ __forceinline__ double fixed_order_sum(const double *__restrict__ part, int n, double *sh) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  int i = threadIdx.x;
+  // eight loads in flight per thread, added in index order
+  for (; i + 7 * 256 < n; i += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[i + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; i < n; i += 256) s += part[i];
   return block_sum<256>(s, sh);
 }
 

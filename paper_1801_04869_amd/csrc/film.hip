@@ -300,7 +300,8 @@ __device__ __forceinline__ void row_tw_put(const RowTw<T, M, THREADS> &rt, const
 // MODE 1: G rows (gdot = G - C, per-block sums of |gdot| on free space,
 //         transform gdot on free space).
 // MODE 2: rows of a double array.
-// MODE 5: rows of a double array minus A on free space.
+// MODE 5: rows of a double array minus A on free space (A summed from the
+//         per-block sums pp.in when given, else it->A).
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -349,7 +350,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     shift = parts_sum(pp.in, pp.nin) * it->inv_nout;
     if (blockIdx.x == 0 && threadIdx.x == 0) it->C = shift;
   }
-  if constexpr (MODE == 5) shift = it->A;
+  if constexpr (MODE == 5) {
+    // A from per-block sums of the input over D (or the value in it->A)
+    shift = pp.in ? parts_sum(pp.in, pp.nin) * it->inv_nout : it->A;
+    if (pp.in && blockIdx.x == 0 && threadIdx.x == 0) it->A = shift;
+  }
   double acc = 0.0, acc_film = 0.0;
   cx<T> v[RMAX];
 #pragma unroll
@@ -941,6 +946,28 @@ __global__ void __launch_bounds__(256) sum_blocks(const double *__restrict__ x, 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Per-block sums of x over kSumWideThreads * kSumWideNpt consecutive entries
+// (512 blocks at 2048^2, few enough for a consuming pass to add them itself);
+// a thread's loads are issued together, its values added in index order.
+constexpr int kSumWideThreads = 1024;
+constexpr int kSumWideNpt = 8;
+__global__ void __launch_bounds__(kSumWideThreads) sum_wide(const double *__restrict__ x, long long n,
+                                                           double *__restrict__ part) {
+  __shared__ double red[kSumWideThreads / 64];
+  const long long i0 = (long long)blockIdx.x * (kSumWideThreads * kSumWideNpt) + threadIdx.x;
+  double v[kSumWideNpt];
+#pragma unroll
+  for (int k = 0; k < kSumWideNpt; ++k) {
+    const long long i = i0 + (long long)k * kSumWideThreads;
+    v[k] = i < n ? x[i] : 0.0;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSumWideNpt; ++k) acc += v[k];
+  const double s = block_total<kSumWideThreads>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // ------------------------------------------------------------ adjoint stencil
 // Transpose of g -> dh_in (eqs. (2), (3), (9)).  For the x-edge (p, q+1/2)
 // and the y-edge (p+1/2, q) of node (p, q): the cotangent of e from the
@@ -1451,7 +1478,6 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   const long long n = c->nnode;
-  const int nb = (int)((n + 255) / 256);
   T *Mu = f.G;   // the forward's G is scratch between calls
   IterState is{};
   is.fixed = c->fixed_iters;
@@ -1459,18 +1485,20 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   is.sum0 = c->tol / (double)n;
   int rc;
   if ((rc = run_iter_init(c, is))) return rc;
-  {
-    ProfScope ps(c, K_VJP);
-    hipLaunchKernelGGL(sum_blocks, dim3(nb), dim3(256), 0, c->stream, ybar, n, c->d_part);
-  }
-  if ((rc = run_finalize_mean(c, nb, 1))) return rc;                  // A = sum_D ybar / #out
-  // regions of d_part: residual, w2 sums, w1 sums (two, alternating), scale
+  // regions of d_part: residual, w2 sums, w1 sums (two, alternating), scale,
+  // sums of ybar
   const int pnb = film_row_blocks<T>(c);
   double *Rr = c->d_part, *Rw2 = c->d_part + pnb, *Rw1[2] = {c->d_part + 2 * pnb, c->d_part + 3 * pnb},
-         *Rsc = c->d_part + 4 * pnb;
+         *Rsc = c->d_part + 4 * pnb, *Ry = c->d_part + 5 * pnb;
+  const int nyb = (int)((n + kSumWideThreads * kSumWideNpt - 1) / (kSumWideThreads * kSumWideNpt));
+  {
+    ProfScope ps(c, K_VJP);
+    hipLaunchKernelGGL(sum_wide, dim3(nyb), dim3(kSumWideThreads), 0, c->stream, ybar, n, Ry);
+  }
   const double inv_nout = is.inv_nout, lam = c->lambda;
-  // mu0 = K1 (ybar - A on free space); C0 = <w1, ybar - A 1_out> / #out
-  if ((rc = film_fwd<T, 5>(c, nullptr, ybar, 0.0, parts(nullptr, 0, Rw1[0]), K_VJP))) return rc;
+  // mu0 = K1 (ybar - A on free space), A = sum_D ybar / #out from the sums
+  // above; C0 = <w1, ybar - A 1_out> / #out
+  if ((rc = film_fwd<T, 5>(c, nullptr, ybar, 0.0, parts(Ry, nyb, Rw1[0]), K_VJP))) return rc;
   if ((rc = film_col<T>(c, 0))) return rc;
   {
     AdjParts ap{Rw1[0], nullptr, nullptr, pnb, inv_nout, 0.0, Rr, Rw2, Rsc};
