@@ -877,6 +877,11 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     if (packed) v[rho] = {base[y].x, base_m[y].x};
     else v[rho] = active ? base[y] : cx<T>{(T)0, (T)0};
   }
+  // |k|^2 terms of the multiplier, loaded with the column
+  T ky2[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) ky2[rho] = (T)k2y[j + rho * TT];
+  const T kxx = (T)k2x[active ? col : 0], kxm = (T)k2x[kx - 1];
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
   auto lidx = [](int i) { return i + (i >> 4); };
   pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, twp);
@@ -892,15 +897,13 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     for (int rho = 0; rho < RMAX; ++rho) xch[lidx(j + rho * TT)] = v[rho];
     __syncthreads();
   }
-  const T kxx = (T)k2x[active ? col : 0], kxm = (T)k2x[kx - 1];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
     const int k = j + rho * TT;
-    const T ky2 = (T)k2y[k];
-    const T m0 = mult(kxx + ky2);
+    const T m0 = mult(kxx + ky2[rho]);
     if (packed) {
       const cx<T> zm = conj(xch[lidx((NY - k) & (NY - 1))]);
-      const T mm = mult(kxm + ky2);
+      const T mm = mult(kxm + ky2[rho]);
       const T hp = (T)0.5 * (m0 + mm), hm = (T)0.5 * (m0 - mm);
       v[rho] = {hp * v[rho].x + hm * zm.x, hp * v[rho].y + hm * zm.y};
     } else {
