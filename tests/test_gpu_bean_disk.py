@@ -1,0 +1,51 @@
+"""End-to-end check of the film path against the Bean model (Sec. 3, first
+example): a thin disk of radius 1 in [-2, 2]^2, power law n = 1000 (close to
+the Bean critical state), rho_out = 1, field ramp h_e = t, integrated on the
+GPU with the adaptive driver from the virgin state to h_e = 0.5.  The sheet
+current |j| in the disk is compared with the Bean solution (flux front
+a = R / cosh(2 h_e / j_c), |j| = j_c between a and R).  The paper reports an
+L1 deviation of 2.2 % on a 128^2 grid with its own implementation; this
+staggered finite-difference form measures about 5 % on the same grid (and
+about 3 % on 256^2); the bound below leaves room for the different
+discretisation while still failing on a wrong current distribution."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import bean  # noqa: E402
+from paper_1801_04869_amd import api  # noqa: E402
+from paper_1801_04869_amd import workloads as W  # noqa: E402
+
+
+def test_disk_current_matches_bean_model():
+    N, L = 128, 2.0
+    mat = W.film_disk(N, N, L, L, 1.0)
+    c = api.Context(2, api.FP64)
+    c.set_grid(N, N, 1, L, L)
+    c.set_domain(torch.from_numpy(mat).cuda())
+    c.set_params(None, 1.0, 1000.0, 1.0, 1.0)
+    c.set_solver(0.7, 2e-4, 100, 0)
+    c.set_field(api.RAMP, (0.0, 0.0, 1.0), 1.0, 1.0, 1.0)
+    g = torch.zeros((N, N), dtype=torch.float64, device="cuda")
+    print("disk 128^2 n=1000: integrating to h_e = 0.5", flush=True)
+    n_steps, _ = c.integrate(g, 0.0, 0.5, 1e-3, 1e-6)
+    _, j, _ = c.observe(g, 0.5, want_hz=False, want_j=True)
+    j = j.cpu().numpy()
+    # |j| at nodes from the mean of the two x-edges and the two y-edges there
+    jxn = 0.5 * (j[0] + np.roll(j[0], 1, axis=0))
+    jyn = 0.5 * (j[1] + np.roll(j[1], 1, axis=1))
+    x = -L + (2 * L / N) * np.arange(N)
+    X, Y = np.meshgrid(x, x)
+    r = np.hypot(X, Y)
+    inside = r < 1.0
+    jb = np.abs(bean.disk_current(r[inside], 1.0, 0.5))
+    jn = np.hypot(jxn, jyn)[inside]
+    dj = np.abs(jn - jb).sum() / np.abs(jb).sum()
+    print("steps %d, L1 deviation of |j| from the Bean disk %.2f %%" % (n_steps, 100 * dj), flush=True)
+    assert n_steps > 100
+    assert dj < 0.08
