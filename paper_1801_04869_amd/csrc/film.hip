@@ -85,8 +85,10 @@ __device__ __forceinline__ T film_edge_e(const double *__restrict__ g, const uin
 constexpr int kStencilNpt = 8;
 constexpr int kStencilThreads = 1024;
 
+// FP32: two blocks of 16 waves per CU (all 512 blocks of 2048^2 at once)
+// need at most 64 registers per lane.
 template <typename T>
-__global__ void __launch_bounds__(kStencilThreads) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+__global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) == 4 ? 8 : 4) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
                                                     T *__restrict__ H, FilmGeom G, FilmLaw law, double hde,
                                                     int warm, double *__restrict__ part) {
@@ -1507,7 +1509,8 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
     AdjParts ap{Rw1[0], nullptr, nullptr, pnb, inv_nout, 0.0, Rr, Rw2, Rsc};
     if ((rc = film_adj<T, 8>(c, Mu, f.w2, ap))) return rc;
   }
-  if ((rc = run_finalize_mean(c, pnb, 2, (int)(Rsc - c->d_part)))) return rc;   // thr = tol mean_D |mu0|
+  // thr = tol mean_D |mu0| (the stop test of a fixed count does not use it)
+  if (c->fixed_iters <= 0 && (rc = run_finalize_mean(c, pnb, 2, (int)(Rsc - c->d_part)))) return rc;
   MAG_HIP(c, hipGetLastError());
   const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
   int issued = 0;
