@@ -81,12 +81,13 @@ __device__ __forceinline__ T film_edge_e(const double *__restrict__ g, const uin
 // keep the warm start (or take dh_e/dt).  Each thread handles kStencilNpt
 // nodes kStencilThreads apart; one partial sum of H - dh_e over D per block
 // (few enough blocks that every block of the next pass can add the partials
-// itself: 512 at 2048^2).
-constexpr int kStencilNpt = 8;
+// itself: 1024 at 2048^2).  Four nodes per thread rather than eight put twice
+// as many waves on the film's rows, whose nodes each gather their
+// neighbourhood in a chain of dependent loads (21.8 -> 20.3 us at 2048^2).
+constexpr int kStencilNpt = 4;
 constexpr int kStencilThreads = 1024;
 
-// FP32: two blocks of 16 waves per CU (all 512 blocks of 2048^2 at once)
-// need at most 64 registers per lane.
+// FP32: two blocks of 16 waves per CU need at most 64 registers per lane.
 template <typename T>
 __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) == 4 ? 8 : 4) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
