@@ -17,7 +17,10 @@ instrumentation; per-kernel durations come from a further loop of the same
 run in which the library attaches HIP start/stop events to the dispatch of
 each transform kernel (hipExtLaunchKernelGGL, so no marker packets are timed
 with the kernel): the breakdown, and the mean duration of the dominant kernel
-(the roofline figure).
+(the roofline figure).  Further figures: the VJP of the same right-hand side
+(adjoint/forward time ratio), adaptive BS23 step attempts on the same grid
+(bs23_step_ms, and its ratio to three right-hand sides enqueued back to
+back), and the error of the mixed form per result on a 256^2 trajectory.
 """
 import argparse
 import json
@@ -193,9 +196,27 @@ def run_gpu(prec, wl, mat, jc, g, steps, warmup, t, fixed=0):
         assert ctx.rhs_vjp(state, t, ybar, gbar, jcbar) == 0, ctx.last_error()
     torch.cuda.synchronize()
     dt_vjp = time.perf_counter() - t2
+    # adaptive BS23 step attempts (mag_step, same fixed count) from the virgin
+    # state g = 0 at t = 0, where every stage stays finite: three right-hand
+    # sides enqueued without host waits, the stage sums, the error norm and
+    # one host synchronisation per attempt
+    y = torch.zeros_like(state)
+    ts, hs = 0.0, 1e-7
+    ctx.reset_warm_start()
+    for _ in range(warmup):
+        ts, hs, _ = ctx.step(y, ts, hs)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    n_acc = 0
+    for _ in range(steps):
+        ts, hs, acc = ctx.step(y, ts, hs)
+        n_acc += acc
+    torch.cuda.synchronize()
+    dt_step = time.perf_counter() - t3
     res = dict(value=steps / dt, ms_per_step=1e3 * dt / steps, inner_iters=float(np.mean(iters)), prof=prof_all,
                dominant=dominant, prof_dom=prof_dom[dominant], out=out.cpu().numpy(),
-               vjp_ms=1e3 * dt_vjp / steps, value_stream=steps / dt_stream)
+               vjp_ms=1e3 * dt_vjp / steps, value_stream=steps / dt_stream, step_ms=1e3 * dt_step / steps,
+               step_accepted=n_acc, step_finite=bool(torch.isfinite(y).all()))
     ctx.close()
     return res
 
@@ -366,6 +387,10 @@ def main():
         line["mixed_vs_fp64_per_result"] = accuracy(wl)
         line["kernels_fp64"] = kernel_table(f64["prof"], n, kx, ny, "fp64", a.iters, n_out)
     line["adjoint_forward_ratio"] = round(m["vjp_ms"] / m["ms_per_step"], 3)
+    line["bs23_step_ms"] = round(m["step_ms"], 4)
+    line["bs23_step_over_3_rhs"] = round(m["step_ms"] * m["value_stream"] / 3e3, 3)
+    line["bs23_steps"] = "%d attempts from g = 0 at t = 0, %d accepted, state finite: %s" % (
+        a.steps, m["step_accepted"], m["step_finite"])
     line["adjoint_ms_per_rhs"] = round(m["vjp_ms"], 4)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, mat, jc, g, a.t, a.iters)

@@ -654,6 +654,29 @@ static int launch_axpy(mag_ctx *c, double *out, const double *y, const double *k
   return MAG_OK;
 }
 
+// Stage evaluations k2..k4 of a step with a fixed inner count (film) are
+// enqueued without a host wait: nothing in them is data-dependent control.
+// The step's one synchronisation then checks the state of the last
+// evaluation, which a non-finite value in any stage reaches through the stage
+// states.  With the stop test every evaluation keeps its host poll.
+static int stage_rhs(mag_ctx *c, const double *y, double t, double *k) {
+  c->rhs_async = c->fixed_iters > 0 && c->dim == 2;
+  const int rc = rhs_impl(c, y, t, k, nullptr);
+  c->rhs_async = false;
+  return rc;
+}
+
+// After a synchronisation: the status of the stages enqueued by stage_rhs.
+static int stages_status(mag_ctx *c) {
+  if (!c->async_pending) return MAG_OK;
+  c->async_pending = false;
+  if (c->h_it->done == 2 || !std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C)) {
+    c->warm_valid = false;
+    return set_error(c, MAG_E_NUMERIC, "non-finite residual");
+  }
+  return MAG_OK;
+}
+
 static int step_impl(mag_ctx *c, double *state, double *t, double *dt, double rtol, double atol, int *accepted) {
   int rc = ensure_rk(c);
   if (rc) return rc;
@@ -671,21 +694,21 @@ static int step_impl(mag_ctx *c, double *state, double *t, double *dt, double rt
   }
   auto failed = [&](int st) { return st == MAG_NOT_CONVERGED || st == MAG_E_NUMERIC; };
   if ((rc = launch_axpy(c, yt, state, k1, nullptr, nullptr, 1.0, 0, 0, 1, kA21 * h))) return rc;
-  rc = rhs_impl(c, yt, *t + kRkC2 * h, k2, nullptr);
+  rc = stage_rhs(c, yt, *t + kRkC2 * h, k2);
   if (failed(rc)) {
     *dt = 0.5 * h;
     return MAG_OK;
   }
   if (rc) return rc;
   if ((rc = launch_axpy(c, yt, state, k2, nullptr, nullptr, 1.0, 0, 0, 1, kA32 * h))) return rc;
-  rc = rhs_impl(c, yt, *t + kRkC3 * h, k3, nullptr);
+  rc = stage_rhs(c, yt, *t + kRkC3 * h, k3);
   if (failed(rc)) {
     *dt = 0.5 * h;
     return MAG_OK;
   }
   if (rc) return rc;
   if ((rc = launch_axpy(c, yn, state, k1, k2, k3, kB1, kB2, kB3, 3, h))) return rc;
-  rc = rhs_impl(c, yn, *t + h, k4, nullptr);
+  rc = stage_rhs(c, yn, *t + h, k4);
   if (failed(rc)) {
     *dt = 0.5 * h;
     return MAG_OK;
@@ -701,6 +724,10 @@ static int step_impl(mag_ctx *c, double *state, double *t, double *dt, double rt
   MAG_HIP(c, hipGetLastError());
   double en = 0.0;
   if ((rc = host_max(c, nb, &en))) return rc;
+  if (failed(stages_status(c))) {
+    *dt = 0.5 * h;
+    return MAG_OK;
+  }
   if (en <= 1.0) {
     MAG_HIP(c, hipMemcpyAsync(state, yn, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     std::swap(c->rk_k1, c->rk_k4);
@@ -736,12 +763,17 @@ int mag_step_fixed(mag_ctx *c, double *state, double t, double dt) {
   c->fsal_valid = false;
   double *k1 = rk_buf(c, 0), *k2 = rk_buf(c, 1), *k3 = rk_buf(c, 2), *yt = rk_buf(c, 4);
   const double h = dt;
-  if ((rc = rhs_impl(c, state, t, k1, nullptr))) return rc;
+  if ((rc = stage_rhs(c, state, t, k1))) return rc;
   if ((rc = launch_axpy(c, yt, state, k1, nullptr, nullptr, 1.0, 0, 0, 1, kA21 * h))) return rc;
-  if ((rc = rhs_impl(c, yt, t + kRkC2 * h, k2, nullptr))) return rc;
+  if ((rc = stage_rhs(c, yt, t + kRkC2 * h, k2))) return rc;
   if ((rc = launch_axpy(c, yt, state, k2, nullptr, nullptr, 1.0, 0, 0, 1, kA32 * h))) return rc;
-  if ((rc = rhs_impl(c, yt, t + kRkC3 * h, k3, nullptr))) return rc;
+  if ((rc = stage_rhs(c, yt, t + kRkC3 * h, k3))) return rc;
   if ((rc = launch_axpy(c, yt, state, k1, k2, k3, kB1, kB2, kB3, 3, h))) return rc;
+  if (c->async_pending) {
+    // the stages' status before the state is overwritten
+    MAG_HIP(c, hipStreamSynchronize(c->stream));
+    if ((rc = stages_status(c))) return rc;
+  }
   return launch_lincomb(c, state, 1.0, yt, 0.0, nullptr, state_len(c));
 }
 

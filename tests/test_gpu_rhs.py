@@ -198,6 +198,40 @@ def test_film_steps_match_oracle():
     assert rel_l2(ygpu, yora) < 1e-10
 
 
+def test_film_steps_fixed_count_match_oracle():
+    """Steps with a fixed inner count: the stage evaluations are enqueued
+    without host waits and the step synchronises once; the accept/reject
+    decisions and the state match the oracle's steps."""
+    case = film_case(64, 64, kind="rect", n=19.0)
+    ctx = make_gpu(case, api.FP64, fixed=3)
+    prob = make_oracle(case, fixed=3)
+    ygpu, yora = _replay_steps(ctx, prob, case, film, [2e-3, 5e-3, 1e-2, 4e-3, 5e-2], 0.1)
+    assert rel_l2(ygpu, yora) < 1e-10
+
+
+def test_film_fixed_count_step_nonfinite_stages():
+    """Non-finite stage values of an asynchronous fixed-count step are seen
+    at the step's synchronisation: mag_step rejects the step and leaves the
+    state alone; mag_step_fixed reports E_NUMERIC with the state unchanged."""
+    case = film_case(64, 64, kind="rect", n=19.0)
+    ctx = make_gpu(case, api.FP64, fixed=3)
+    s = torch.from_numpy(case["state"]).cuda()
+    t, dt, acc = ctx.step(s, 0.1, 1e300)    # the stage states overflow
+    assert not acc and t == 0.1 and dt == 0.5e300
+    assert np.array_equal(s.cpu().numpy(), case["state"])
+    bad = case["state"].copy()
+    q, p = np.argwhere(make_oracle(case).in_node)[0]
+    bad[q, p] = np.nan
+    sb = torch.from_numpy(bad).cuda()
+    with pytest.raises(api.MagError) as e:
+        ctx.step_fixed(sb, 0.1, 1e-3)
+    assert e.value.code == api.E_NUMERIC
+    assert np.array_equal(sb.cpu().numpy(), bad, equal_nan=True)
+    # the context stays usable
+    t, dt, acc = ctx.step(s, 0.1, 1e-4)
+    assert t == (0.1 + 1e-4 if acc else 0.1) and np.isfinite(s.cpu().numpy()).all()
+
+
 @BULK_OFF
 def test_bulk_steps_match_oracle():
     case = bulk_case(32, 32, 32, n=25.0)
