@@ -145,8 +145,11 @@ int mag_rhs_status(mag_ctx *ctx, int *n_inner);
  * size either way.  Error norm max_i |err_i| / max(rtol max(|y_i|,|ynew_i|),
  * atol); step factor min(5, max(0.2, 0.8 err^(-1/3))) after acceptance,
  * max(0.2, 0.8 err^(-1/3)) after rejection, 1/2 when an inner iteration did
- * not converge.  The first-same-as-last stage is reused while state and *t
- * are unchanged since the previous accepted call. */
+ * not converge or a stage value is not finite.  The first-same-as-last stage
+ * is reused while state and *t are unchanged since the previous accepted
+ * call.  With a fixed inner count (film) the stages after the first are
+ * enqueued without host waits and the call synchronises once, for the error
+ * norm; with the stop test each stage polls the host as mag_rhs does. */
 int mag_step(mag_ctx *ctx, double *state, double *t, double *dt, double rtol, double atol,
              int *accepted);
 
@@ -189,7 +192,10 @@ int mag_set_warm_start(mag_ctx *ctx, int on);
 
 /* One Bogacki-Shampine step of exactly dt from (state, t), without error
  * control (replay of an accepted step): state (device) advances in place.
- * Returns MAG_NOT_CONVERGED (state unchanged) if an inner iteration fails. */
+ * Returns MAG_NOT_CONVERGED if an inner iteration fails, MAG_E_NUMERIC if a
+ * stage value is not finite; the state is unchanged in both cases.  With a
+ * fixed inner count (film) the three stages are enqueued without host waits
+ * and the call synchronises once, before the state is written. */
 int mag_step_fixed(mag_ctx *ctx, double *state, double t, double dt);
 
 /* Transpose of mag_step_fixed at (state, t, dt) with dt frozen: ybar
