@@ -425,7 +425,8 @@ int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, doubl
   if (!(Lx > 0) || !(Ly > 0) || (c->dim == 3 && !(Lz > 0))) return set_error(c, MAG_E_ARG, "box half-lengths must be positive");
   if (c->dim == 3 && !MAG_BULK_ENABLE)
     return set_error(c, MAG_E_STATE,
-                     "the 3D path is disabled in this build (held off the GPU after an unexplained memory fault)");
+                     "the 3D path is disabled (held off the GPU after an unexplained memory fault; "
+                     "MAG_BULK_ENABLE compiles it in)");
   MAG_HIP(c, hipStreamSynchronize(c->stream));
   IterState *keep_it = c->d_it;
   c->d_it = nullptr;
