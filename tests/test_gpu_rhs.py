@@ -134,6 +134,30 @@ def test_film_rhs_fixed_iterations(prec, ci, fixed):
     assert rel_l2(out, ref) < TOL[prec]
 
 
+EDGE_SHAPES = [
+    dict(nx=16, ny=16, kind="rect"),
+    dict(nx=16, ny=2048, L=(0.25, 2.0), kind="offrect", jc_s=0.2),
+    dict(nx=2048, ny=16, L=(2.0, 0.25), kind="offrect", jc_s=0.2),
+]
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("ci", range(len(EDGE_SHAPES)))
+def test_film_rhs_extreme_shapes(prec, ci):
+    """The smallest grid and the most elongated ones: row passes with fewer
+    rows than one block holds, column passes of 2048 with 8 pencils and of 16
+    with 1024 pencils, a single stencil block.  Fixed count (the stop test is
+    not reached on the elongated grids, by the oracle either)."""
+    case = film_case(**EDGE_SHAPES[ci])
+    print("film edge shape", case["n"], prec, flush=True)
+    ctx = make_gpu(case, prec, fixed=2)
+    prob = make_oracle(case, fixed=2)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.1)
+    ref, rit, rst = _ora_rhs(prob, case, 0.1)
+    assert st == 0 and rst == 0 and it == rit == 2
+    assert rel_l2(out, ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
 def test_film_rhs_converged_sequence(prec):
     case = film_case(128, 128, kind="rect", jc_s=0.2)
@@ -320,6 +344,10 @@ def test_argument_and_state_errors():
     c.set_grid(32, 32, 1, 1, 1)
     with pytest.raises(api.MagError) as e:
         c.set_domain(torch.zeros(32, 32, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == api.E_ARG
+    # a film that leaves no free space (the free-space iteration is void)
+    with pytest.raises(api.MagError) as e:
+        c.set_domain(torch.ones(32, 32, dtype=torch.uint8, device="cuda"))
     assert e.value.code == api.E_ARG
     bad = torch.full((32, 32), 3, dtype=torch.uint8, device="cuda")
     with pytest.raises(api.MagError) as e:
