@@ -600,7 +600,6 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
                     const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
                     FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it, int keep,
                     double *__restrict__ res) {
-  if (it->done) return;
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
   constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
@@ -622,6 +621,10 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   tile_fetch(tr, S, G.ny, q0);
   RowTw<T, M, RS::THREADS> rtw;
   row_tw_fetch(rtw, twM, twN);
+  // the stop flag is tested after the tile and twiddle loads are issued (they
+  // do not depend on it and nothing is written before the test), so its load
+  // does not delay theirs: -0.2 / -0.4 us on passes 2 / 4 at 2048^2
+  if (it->done) return;
   double cst;
   if constexpr (MODE == 6) {
     cst = parts_sum(pp.in, pp.nin) * it->inv_nout;   // C
