@@ -844,12 +844,12 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     film_cols(cx<T> *__restrict__ S, int kx, const double *__restrict__ k2x, const double *__restrict__ k2y,
               double inv_n, int which, const cx<T> *__restrict__ tw, Parts pp, IterState *__restrict__ it,
               IterState *mirror) {
-  if (it->done) return;
   using CS = FilmColShape<NY, T>;
   using PL = typename CS::PL;
   constexpr int TT = CS::TT, P = CS::P, RMAX = PL::RMAX, PITCH = CS::PITCH;
   __shared__ __align__(16) T lds[CS::LDS_T];
   if (pp.in) {
+    if (it->done) return;
     // Stop test of Sec. 2.3 on the residual sums of the previous pass: every
     // block takes the same decision; block 0 records it.
     const double r = parts_sum(pp.in, pp.nin) * it->inv_nout;
@@ -888,6 +888,9 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) ky2[rho] = (T)k2y[j + rho * TT];
   const T kxx = (T)k2x[active ? col : 0], kxm = (T)k2x[kx - 1];
+  // without a decision in this pass the stop flag is tested once the
+  // column's loads are issued (nothing is written before the test)
+  if (!pp.in && it->done) return;
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
   auto lidx = [](int i) { return i + (i >> 4); };
   pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, twp);
