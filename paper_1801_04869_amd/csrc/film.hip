@@ -310,7 +310,6 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
                   cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
                   FilmGeom G, double hde, Parts pp, IterState *__restrict__ it, const T *__restrict__ w1) {
-  if (it->done) return;
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
   constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
@@ -341,6 +340,9 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       w0[rho][1] = wsrc[o + 1];
     }
   }
+  // the stop flag is tested once the loads above are issued (nothing is
+  // written before the test)
+  if (it->done) return;
   // MODE 0: the shift A of (10) from the previous update's sums (or the
   // stencil's, already reduced into it->A); MODE 1: C = free-space mean of G.
   double shift = 0.0;
@@ -467,7 +469,6 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_adj(T *__restrict__ X, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
                   const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
                   FilmGeom G, double lam, AdjParts pp, IterState *__restrict__ it) {
-  if (it->done) return;
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
   constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
@@ -485,6 +486,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   tile_fetch(tr, S, G.ny, q0);
   RowTw<T, M, RS::THREADS> rtw;
   row_tw_fetch(rtw, twM, twN);
+  if (it->done) return;   // after the loads are issued; nothing written before
   double c_new = 0.0, c_old = 0.0, a_z = 0.0;
   if constexpr (MODE == 8) {
     c_new = pp.c_new * parts_sum(pp.in_new, pp.nin);
@@ -849,10 +851,11 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   constexpr int TT = CS::TT, P = CS::P, RMAX = PL::RMAX, PITCH = CS::PITCH;
   __shared__ __align__(16) T lds[CS::LDS_T];
   if (pp.in) {
-    if (it->done) return;
     // Stop test of Sec. 2.3 on the residual sums of the previous pass: every
-    // block takes the same decision; block 0 records it.
+    // block takes the same decision; block 0 records it.  The flag of an
+    // earlier stop is tested once the sums are loaded.
     const double r = parts_sum(pp.in, pp.nin) * it->inv_nout;
+    if (it->done) return;
     const int iters = pp.iter + 1;
     const int fixed = it->fixed;
     const int done = !isfinite(r) ? 2 : (fixed > 0 ? (iters >= fixed ? 1 : 0) : (r < it->thr ? 1 : 0));
