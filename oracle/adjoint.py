@@ -13,7 +13,8 @@ Writing x = dh - dh_e on all nodes, the iteration is linear in x:
 
 with Q = (I - 1 m_out^T) K1 (eq. (11) and the constant C that removes the
 free-space mean of gdot), P_out the free-space mask, K1 = F^{-1} 2/|k| F and
-K2 = F^{-1} |k|/2 F (real symmetric operators), m_out = 1_out / #out, and
+K2 = F^{-1} |k|/2 exp(-|k|^2 sigma^2/2) F (the smoothed multiplier of (12);
+real symmetric operators), m_out = 1_out / #out, and
 S = I - 1_out 1^T / #out the shift A of (10) that makes sum_D x = 0.  The
 warm start and dh_e only add constants, so the derivative of k evaluations of
 (11) with k - 1 updates (12) in between is
@@ -119,7 +120,7 @@ def film_iteration_vjp(prob, ybar, k=None):
     if k is not None:
         for _ in range(k - 1):
             nu = ST(mu)
-            w = film.apply_multiplier(np.where(out, nu, 0.0), prob.K2)
+            w = film.apply_multiplier(np.where(out, nu, 0.0), prob.K2s)
             mu = nu - lam * QT(np.where(out, w, 0.0))
             steps += 1
     else:
@@ -130,7 +131,7 @@ def film_iteration_vjp(prob, ybar, k=None):
             if steps >= prob.max_inner - 1:
                 status = NOT_CONVERGED
                 break
-            w = film.apply_multiplier(np.where(out, nu, 0.0), prob.K2)
+            w = film.apply_multiplier(np.where(out, nu, 0.0), prob.K2s)
             mu = nu - lam * QT(np.where(out, w, 0.0))
             steps += 1
     xbar = ST(mu)

@@ -21,13 +21,27 @@ Discretisation (the staggered finite-difference form of the method of lines):
   div(rho grad g) at in-nodes.
 
 Iteration (10)-(12) with the Fourier multipliers 2/|k| (eq. (7)) and |k|/2
-(eq. (12)), both zero at k = 0, on the FFT grid k = 2 pi fftfreq(n, d).
+(eq. (12)), both zero at k = 0, on the FFT grid k = 2 pi fftfreq(n, d).  The
+update (12) may carry the Gaussian filter exp(-|k|^2 sigma^2 / 2) that Sec.
+2.2 applies to its spectral derivatives and, in the same way, to (12)
+(``sigma``; the paper's value is sqrt(dx^2 + dy^2), see ``paper_sigma``).
+The staggered form leaves it off by default (sigma = 0): with unsmoothed
+finite differences inside the film the filtered update cannot correct the
+high-|k| part of the free-space error and the residual stalls.  The filter
+only preconditions the update: the converged gdot (zero in free space, eq.
+(10)) does not depend on it.  The post-processing h_z of Sec. 2.1 uses the
+plain |k|/2.
 """
 import numpy as np
 
 from .field import AppliedField
 
 OK, NOT_CONVERGED = 0, 1
+
+
+def paper_sigma(dx, dy):
+    """Width of the Gaussian filter chosen in Sec. 2.2: sqrt(dx^2 + dy^2)."""
+    return float(np.hypot(dx, dy))
 
 
 def shift(a, axis, off):
@@ -43,7 +57,7 @@ class FilmProblem:
     """
 
     def __init__(self, nx, ny, Lx, Ly, material, jc_cell=None, jc0=1.0, n=19.0, e0=1.0,
-                 rho_out=1.0, lam=0.7, tol=2e-4, max_inner=100, fixed_iters=0, field=None):
+                 rho_out=1.0, lam=0.7, tol=2e-4, max_inner=100, fixed_iters=0, field=None, sigma=0.0):
         self.nx, self.ny = int(nx), int(ny)
         self.Lx, self.Ly = float(Lx), float(Ly)
         self.dx, self.dy = 2.0 * self.Lx / self.nx, 2.0 * self.Ly / self.ny
@@ -54,6 +68,8 @@ class FilmProblem:
         self.lam, self.tol = float(lam), float(tol)
         self.max_inner, self.fixed_iters = int(max_inner), int(fixed_iters)
         self.field = field if field is not None else AppliedField()
+        # Gaussian filter of the update (12), Sec. 2.2 (None: the paper's sqrt(dx^2 + dy^2))
+        self.sigma = float(paper_sigma(self.dx, self.dy) if sigma is None else sigma)
         self.warm = None
         self._classify()
         self._symbols()
@@ -82,7 +98,9 @@ class FilmProblem:
         self.K1 = np.zeros_like(kabs)
         nz = kabs > 0
         self.K1[nz] = 2.0 / kabs[nz]          # eq. (7): 2/|k|, set to 0 at k = 0
-        self.K2 = 0.5 * kabs                  # eq. (12): |k|/2 (0 at k = 0)
+        self.K2 = 0.5 * kabs                  # |k|/2 (0 at k = 0): h_z of Sec. 2.1
+        # eq. (12) with the Gaussian smoothing of Sec. 2.2
+        self.K2s = self.K2 * np.exp(-0.5 * (self.sigma * kabs) ** 2)
 
     def reset_warm_start(self):
         self.warm = None
@@ -172,8 +190,8 @@ def rhs(prob, g, t):
             prob.warm = H.copy()
             return gdot, i + 1, OK
         U = np.where(out, gdot, 0.0)                         # gdot_out of (12)
-        V = apply_multiplier(U, prob.K2)
-        H[out] -= prob.lam * V[out]                          # relaxed update (12)
+        V = apply_multiplier(U, prob.K2s)
+        H[out] -= prob.lam * V[out]                          # relaxed, smoothed update (12)
         H[out] -= (H - hde).sum() / nout                     # A^i restores (10)
     prob.warm = None
     return None, kmax, NOT_CONVERGED

@@ -3,15 +3,39 @@
 // sources run on the host under AddressSanitizer, one work-group at a time
 // with one std::thread per work-item, so that every global, LDS and
 // dynamic-LDS access is bounds-checked.  Nothing in the product links it.
+//
+// Device memory is modelled as a separate address space:
+//  * hipMalloc / hipMallocAsync allocations are registered as DEVICE memory
+//    and ASan-poisoned whenever host code runs, so a host read or write of
+//    device memory stops the run with a use-after-poison report;
+//  * hipHostMalloc allocations are registered as PINNED host memory
+//    (readable by both sides);
+//  * every pointer argument of a launch, and every pointer member of a
+//    by-value struct argument, must be null or lie inside a live DEVICE or
+//    PINNED allocation (a plain host pointer reaching a kernel is a GPU page
+//    fault);
+//  * every hipMemcpy* kind is checked against the registry;
+//  * launch shapes are checked against the hardware limits (block <= 1024
+//    work-items, grid.x * block.x < 2^32) and logged, so that the test can
+//    compare them with the gfx950 code-object metadata of the same kernels
+//    (max flat work-group size, static LDS).
 #pragma once
+#include <sanitizer/asan_interface.h>
+
 #include <barrier>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <dlfcn.h>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <thread>
+#include <tuple>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #define __global__
@@ -72,15 +96,161 @@ using std::sqrt;
 typedef int hipError_t;
 typedef void *hipStream_t;
 typedef void *hipEvent_t;
-enum { hipSuccess = 0, hipErrorOutOfMemory = 2 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
 enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
 
-// Fresh device allocations are filled with 0xff bytes (NaN for float and
-// double) so that reads of never-written device memory show up in results.
-inline hipError_t hipMalloc(void *p, size_t n) {
+// ------------------------------------------------------------ allocation registry
+namespace emu {
+enum Kind { HOST = 0, DEVICE = 1, PINNED = 2 };
+struct Alloc {
+  size_t n;
+  int kind;
+};
+inline std::map<uintptr_t, Alloc> &reg() {
+  static std::map<uintptr_t, Alloc> m;
+  return m;
+}
+inline std::mutex &reg_mu() {
+  static std::mutex m;
+  return m;
+}
+inline int violations = 0;
+
+[[noreturn]] inline void fail(const char *fmt, const void *p, const char *what) {
+  fprintf(stderr, "EMU-VIOLATION: ");
+  fprintf(stderr, fmt, p, what);
+  fprintf(stderr, "\n");
+  fflush(stderr);
+  std::abort();
+}
+
+// Kind of the allocation holding p (HOST when none does); *base/*len when found.
+inline int kind_of(const void *p, uintptr_t *base = nullptr, size_t *len = nullptr) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  auto &m = reg();
+  auto it = m.upper_bound(a);
+  if (it == m.begin()) return HOST;
+  --it;
+  if (a >= it->first && a < it->first + (it->second.n ? it->second.n : 1)) {
+    if (base) *base = it->first;
+    if (len) *len = it->second.n;
+    return it->second.kind;
+  }
+  return HOST;
+}
+
+inline void poison_device(bool on) {
+  for (auto &kv : reg())
+    if (kv.second.kind == DEVICE && kv.second.n) {
+      if (on) ASAN_POISON_MEMORY_REGION(reinterpret_cast<void *>(kv.first), kv.second.n);
+      else ASAN_UNPOISON_MEMORY_REGION(reinterpret_cast<void *>(kv.first), kv.second.n);
+    }
+}
+
+inline void *reg_alloc(size_t n, int kind) {
   void *q = std::malloc(n ? n : 1);
-  std::memset(q, 0xff, n ? n : 1);
-  *reinterpret_cast<void **>(p) = q;
+  std::memset(q, 0xff, n ? n : 1);   // NaN bytes: reads of never-written memory show up
+  reg()[reinterpret_cast<uintptr_t>(q)] = Alloc{n, kind};
+  if (kind == DEVICE && n) ASAN_POISON_MEMORY_REGION(q, n);
+  return q;
+}
+
+inline hipError_t reg_free(void *p, int want) {
+  if (!p) return hipSuccess;
+  auto &m = reg();
+  auto it = m.find(reinterpret_cast<uintptr_t>(p));
+  if (it == m.end()) fail("free of %p, which is not the start of a live allocation (%s)", p, want == DEVICE ? "hipFree" : "hipHostFree");
+  if (it->second.kind != want)
+    fail("%p freed with the wrong call (%s)", p, want == DEVICE ? "hipFree on pinned memory" : "hipHostFree on device memory");
+  if (it->second.n) ASAN_UNPOISON_MEMORY_REGION(p, it->second.n);
+  m.erase(it);
+  std::free(p);
+  return hipSuccess;
+}
+
+// A pointer argument of a kernel: null, or inside a live device / pinned allocation.
+inline void check_ptr(const void *p, const char *kname, int argi) {
+  if (!p) return;
+  const int k = kind_of(p);
+  if (k == DEVICE || k == PINNED) return;
+  char what[256];
+  snprintf(what, sizeof what, "%s, argument %d", kname, argi);
+  fail("host pointer %p passed to a kernel (%s)", p, what);
+}
+
+// Members of a by-value struct argument, found by aggregate decomposition
+// (the kernel-argument structs are aggregates of scalars and pointers), so
+// that padding bytes are never taken for addresses.
+struct any_t {
+  template <class U>
+  constexpr operator U() const noexcept;
+};
+template <class T, class Seq, class = void>
+struct ctor_n : std::false_type {};
+template <class T, size_t... I>
+struct ctor_n<T, std::index_sequence<I...>, std::void_t<decltype(T{((void)I, any_t{})...})>> : std::true_type {};
+template <class T, size_t N = 0>
+constexpr size_t field_count() {
+  if constexpr (N < 24 && ctor_n<T, std::make_index_sequence<N + 1>>::value) return field_count<T, N + 1>();
+  else return N;
+}
+#define EMU_FIELDS(N, ...)                     \
+  if constexpr (n == N) {                      \
+    const auto &[__VA_ARGS__] = t;             \
+    emu_visit(f, __VA_ARGS__);                 \
+  }
+template <class F, class... X>
+inline void emu_visit(F &&f, const X &...x) {
+  (f(x), ...);
+}
+template <class T, class F>
+inline void for_each_field(const T &t, F &&f) {
+  constexpr size_t n = field_count<T>();
+  static_assert(n >= 1 && n <= 16, "kernel-argument struct not decomposable");
+  EMU_FIELDS(1, a0)
+  EMU_FIELDS(2, a0, a1)
+  EMU_FIELDS(3, a0, a1, a2)
+  EMU_FIELDS(4, a0, a1, a2, a3)
+  EMU_FIELDS(5, a0, a1, a2, a3, a4)
+  EMU_FIELDS(6, a0, a1, a2, a3, a4, a5)
+  EMU_FIELDS(7, a0, a1, a2, a3, a4, a5, a6)
+  EMU_FIELDS(8, a0, a1, a2, a3, a4, a5, a6, a7)
+  EMU_FIELDS(9, a0, a1, a2, a3, a4, a5, a6, a7, a8)
+  EMU_FIELDS(10, a0, a1, a2, a3, a4, a5, a6, a7, a8, a9)
+  EMU_FIELDS(11, a0, a1, a2, a3, a4, a5, a6, a7, a8, a9, a10)
+  EMU_FIELDS(12, a0, a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11)
+  EMU_FIELDS(13, a0, a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11, a12)
+  EMU_FIELDS(14, a0, a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11, a12, a13)
+  EMU_FIELDS(15, a0, a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11, a12, a13, a14)
+  EMU_FIELDS(16, a0, a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11, a12, a13, a14, a15)
+}
+#undef EMU_FIELDS
+
+template <typename A>
+inline void check_arg(const A &a, const char *kname, int argi) {
+  if constexpr (std::is_pointer_v<A>) {
+    check_ptr(reinterpret_cast<const void *>(a), kname, argi);
+  } else if constexpr (std::is_class_v<A>) {
+    for_each_field(a, [&](const auto &m) { check_arg(m, kname, argi); });
+  }
+}
+
+// Launch log: one line per launch (kernel address relative to its object,
+// grid, block, dynamic LDS), written when EMU_LAUNCH_LOG names a file.
+inline FILE *launch_log() {
+  static FILE *f = nullptr;
+  static bool init = false;
+  if (!init) {
+    init = true;
+    const char *p = getenv("EMU_LAUNCH_LOG");
+    if (p && *p) f = fopen(p, "a");
+  }
+  return f;
+}
+}  // namespace emu
+
+inline hipError_t hipMalloc(void *p, size_t n) {
+  *reinterpret_cast<void **>(p) = emu::reg_alloc(n, emu::DEVICE);
   return hipSuccess;
 }
 template <typename T>
@@ -90,13 +260,87 @@ inline float rsqrtf(float x) { return 1.0f / std::sqrt(x); }
 #define MAG_OPAQUE(x) asm volatile("" : "+m"(x))
 #define MAG_WAVES_PER_EU(...)
 #define hipHostMallocCoherent 0x40000000u
-inline hipError_t hipHostMalloc(void *p, size_t n, unsigned = 0) { return hipMalloc(p, n); }
-inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
-inline hipError_t hipFreeAsync(void *p, hipStream_t) { std::free(p); return hipSuccess; }
-inline hipError_t hipHostFree(void *p) { std::free(p); return hipSuccess; }
-inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { std::memcpy(d, s, n); return hipSuccess; }
-inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t) { std::memcpy(d, s, n); return hipSuccess; }
-inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipHostMalloc(void *p, size_t n, unsigned = 0) {
+  *reinterpret_cast<void **>(p) = emu::reg_alloc(n, emu::PINNED);
+  return hipSuccess;
+}
+inline hipError_t hipFree(void *p) { return emu::reg_free(p, emu::DEVICE); }
+inline hipError_t hipFreeAsync(void *p, hipStream_t) { return emu::reg_free(p, emu::DEVICE); }
+inline hipError_t hipHostFree(void *p) { return emu::reg_free(p, emu::PINNED); }
+
+namespace emu {
+// Copy with the kind checked against the registry: a device side must be a
+// device (or pinned) allocation holding all n bytes, a host side must not be
+// device memory.
+inline hipError_t checked_copy(void *d, const void *s, size_t n, hipMemcpyKind kind, const char *call) {
+  if (n == 0) return hipSuccess;
+  uintptr_t db = 0, sb = 0;
+  size_t dl = 0, sl = 0;
+  const int dk = kind_of(d, &db, &dl), sk = kind_of(s, &sb, &sl);
+  auto need_dev = [&](int k, uintptr_t base, size_t len, const void *p, const char *side) {
+    if (k != DEVICE && k != PINNED) fail("%p is not device memory (%s)", p, side);
+    if (reinterpret_cast<uintptr_t>(p) + n > base + len) fail("copy runs past the end of the allocation at %p (%s)", p, side);
+  };
+  auto need_host = [&](int k, const void *p, const char *side) {
+    if (k == DEVICE) fail("%p is device memory, the copy kind says host (%s)", p, side);
+  };
+  char w[128];
+  switch (kind) {
+    case hipMemcpyHostToDevice:
+      snprintf(w, sizeof w, "%s H2D destination", call);
+      need_dev(dk, db, dl, d, w);
+      snprintf(w, sizeof w, "%s H2D source", call);
+      need_host(sk, s, w);
+      break;
+    case hipMemcpyDeviceToHost:
+      snprintf(w, sizeof w, "%s D2H source", call);
+      need_dev(sk, sb, sl, s, w);
+      snprintf(w, sizeof w, "%s D2H destination", call);
+      need_host(dk, d, w);
+      break;
+    case hipMemcpyDeviceToDevice:
+      snprintf(w, sizeof w, "%s D2D destination", call);
+      need_dev(dk, db, dl, d, w);
+      snprintf(w, sizeof w, "%s D2D source", call);
+      need_dev(sk, sb, sl, s, w);
+      break;
+    case hipMemcpyHostToHost:
+      snprintf(w, sizeof w, "%s H2H", call);
+      need_host(dk, d, w);
+      need_host(sk, s, w);
+      break;
+    default:
+      if (dk == DEVICE) need_dev(dk, db, dl, d, call);
+      if (sk == DEVICE) need_dev(sk, sb, sl, s, call);
+      break;
+  }
+  if (dk == DEVICE) ASAN_UNPOISON_MEMORY_REGION(d, n);
+  if (sk == DEVICE) ASAN_UNPOISON_MEMORY_REGION(const_cast<void *>(s), n);
+  std::memmove(d, s, n);
+  if (dk == DEVICE) poison_device(true);
+  if (sk == DEVICE) poison_device(true);
+  return hipSuccess;
+}
+}  // namespace emu
+
+inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind k) {
+  return emu::checked_copy(d, s, n, k, "hipMemcpy");
+}
+inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
+  return emu::checked_copy(d, s, n, k, "hipMemcpyAsync");
+}
+inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) {
+  if (n == 0) return hipSuccess;
+  uintptr_t b = 0;
+  size_t l = 0;
+  const int k = emu::kind_of(d, &b, &l);
+  if (k != emu::DEVICE && k != emu::PINNED) emu::fail("hipMemsetAsync on %p, which is %s", d, "not device memory");
+  if (reinterpret_cast<uintptr_t>(d) + n > b + l) emu::fail("hipMemsetAsync at %p runs past %s", d, "the end of its allocation");
+  if (k == emu::DEVICE) ASAN_UNPOISON_MEMORY_REGION(d, n);
+  std::memset(d, v, n);
+  if (k == emu::DEVICE) emu::poison_device(true);
+  return hipSuccess;
+}
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline const char *hipGetErrorString(hipError_t) { return "emu"; }
@@ -108,9 +352,27 @@ inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) { *ms =
 template <typename... KA, typename... A>
 void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t shm, A... args) {
   const unsigned nt = b.x * b.y * b.z;
+  Dl_info di{};
+  dladdr(reinterpret_cast<void *>(k), &di);
+  const uintptr_t off = reinterpret_cast<uintptr_t>(k) - reinterpret_cast<uintptr_t>(di.dli_fbase);
+  char kname[64];
+  snprintf(kname, sizeof kname, "kernel at +0x%lx", (unsigned long)off);
+  if (nt == 0 || nt > 1024 || g.x == 0 || g.y == 0 || g.z == 0 || g.y > 65535 || g.z > 65535 ||
+      (unsigned long long)g.x * b.x >= (1ull << 32))
+    emu::fail("launch shape out of the hardware limits (%p, %s)", reinterpret_cast<void *>(k), kname);
+  if (FILE *f = emu::launch_log()) {
+    fprintf(f, "%lx %u %u %u %u %u %u %zu\n", (unsigned long)off, g.x, g.y, g.z, b.x, b.y, b.z, shm);
+    fflush(f);
+  }
+  // kernel arguments converted to the kernel's parameter types, then checked
+  std::tuple<std::decay_t<KA>...> conv(args...);
+  {
+    int i = 0;
+    std::apply([&](const auto &...x) { (emu::check_arg(x, kname, i++), ...); }, conv);
+  }
+  emu::poison_device(false);
   emu::bDim = b;
   emu::gDim = g;
-  std::vector<unsigned char> dynbuf;
   for (unsigned bz = 0; bz < g.z; ++bz)
     for (unsigned by = 0; by < g.y; ++by)
       for (unsigned bx = 0; bx < g.x; ++bx) {
@@ -127,11 +389,29 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t shm, A... args) {
           th.emplace_back([&, t]() {
             emu::tIdx = dim3(t % b.x, (t / b.x) % b.y, t / (b.x * b.y));
             emu::bIdx = dim3(bx, by, bz);
-            k(args...);
+            std::apply(k, conv);
             br.arrive_and_drop();
           });
         for (auto &x : th) x.join();
         std::free(d);
       }
+  emu::poison_device(true);
 }
 #define hipLaunchKernelGGL(K, G, B, S, STREAM, ...) emu_launch(K, dim3(G), dim3(B), (size_t)(S), __VA_ARGS__)
+
+// Entry points for the test driver: device buffers and copies in the
+// emulated device address space.
+extern "C" {
+inline __attribute__((visibility("default"), used)) void *emu_dev_alloc(size_t n) {
+  void *p = nullptr;
+  hipMalloc(&p, n);
+  return p;
+}
+inline __attribute__((visibility("default"), used)) void emu_dev_free(void *p) { hipFree(p); }
+inline __attribute__((visibility("default"), used)) void emu_h2d(void *d, const void *s, size_t n) {
+  hipMemcpy(d, s, n, hipMemcpyHostToDevice);
+}
+inline __attribute__((visibility("default"), used)) void emu_d2h(void *d, const void *s, size_t n) {
+  hipMemcpy(d, s, n, hipMemcpyDeviceToHost);
+}
+}

@@ -1,10 +1,17 @@
 """CPU bounds check of the HIP sources: the library is compiled as host C++
 with AddressSanitizer and UndefinedBehaviorSanitizer against a small emulation
-of the HIP runtime (one CPU thread per work-item, real barriers), then run on
-small film and bulk cases and compared with the FP64 oracle.
+of the HIP runtime (one CPU thread per work-item, real barriers, device memory
+as a separate, poisoned address space, kernel pointer arguments and copy
+kinds checked against the allocation registry), then run on small film and
+bulk cases and compared with the FP64 oracle.  The launch shapes it records
+are then checked against the gfx950 code objects of the same sources
+(work-items per group within the compiled bound, static plus dynamic LDS
+within the per-group limit).
 
-This is the only place the 3D path runs: it is held off the GPU (see the note
-in capi.hip), and the emulation build alone enables it."""
+The 3D path runs only here: it is held off the GPU (see the note in
+capi.hip), and the emulation build alone enables it.  "bulk32" is the first
+bulk case of the GPU parity tests (32^3 cube in a 32^3 grid, FP64, one inner
+iteration)."""
 import os
 import shutil
 import subprocess
@@ -23,8 +30,8 @@ def _libasan():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("which", ["film", "bulk"])
-def test_emulated_kernels_in_bounds_and_match_oracle(which):
+@pytest.mark.parametrize("which", ["film", "bulk", "bulk32"])
+def test_emulated_kernels_in_bounds_and_match_oracle(which, tmp_path):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     asan = _libasan()
@@ -33,13 +40,22 @@ def test_emulated_kernels_in_bounds_and_match_oracle(which):
     sys.path.insert(0, ROOT)
     from tests.emu import build_emu
     lib = build_emu.build(asan=True)
+    log = str(tmp_path / "launches.log")
     env = dict(os.environ)
     env["LD_PRELOAD"] = asan
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
     env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    env["EMU_LAUNCH_LOG"] = log
     r = subprocess.run([sys.executable, os.path.join(HERE, "emu", "emu_driver.py"), lib, which],
-                       capture_output=True, text=True, env=env, cwd=ROOT, timeout=1200)
+                       capture_output=True, text=True, env=env, cwd=ROOT, timeout=1800)
     print(r.stdout[-4000:])
     print(r.stderr[-4000:])
     assert r.returncode == 0
     assert "EMU_DONE fails=0" in r.stdout
+    if shutil.which(os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")) is None:
+        return
+    from tests.emu import kernel_limits
+    seen, problems = kernel_limits.check(lib, log, os.path.join(ROOT, "paper_1801_04869_amd", "csrc"),
+                                         ["capi.hip", "film.hip", "bulk.hip"])
+    assert seen
+    assert not problems, problems
