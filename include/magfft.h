@@ -230,6 +230,15 @@ int mag_prof_enable(mag_ctx *ctx, int on);
 int mag_prof_read(mag_ctx *ctx, int id, int *count, double *total_ms);
 const char *mag_prof_kernel_name(int id);
 
+/* Counts of the work done since the last reset: *n_rhs right-hand sides
+ * evaluated (mag_rhs and the stages of mag_step / mag_integrate /
+ * mag_step_fixed) and *n_inner inner iterations (evaluations of (11) in 2D,
+ * updates (18) in 3D) summed over them; a fixed count enqueued without a
+ * host wait counts its fixed number.  reset != 0 zeroes the counts after
+ * reading them.  Host pointers; either may be NULL.  Instrumentation for
+ * reporting the mean inner iteration count, no GPU work. */
+int mag_stats(mag_ctx *ctx, int reset, long long *n_rhs, long long *n_inner);
+
 #ifdef __cplusplus
 }
 #endif

@@ -168,6 +168,12 @@ class Context:
         self._check(self._L.mag_observe_vjp(self._h, _ptr(hz_bar, torch.float64), _ptr(state_bar, torch.float64)))
 
     # ---------------------------------------------------------- instrumentation
+    def stats(self, reset=False):
+        """(right-hand sides, inner iterations) evaluated since the last reset."""
+        a, b = ctypes.c_longlong(0), ctypes.c_longlong(0)
+        self._check(self._L.mag_stats(self._h, 1 if reset else 0, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def prof_enable(self, on=True, only=None):
         """Record HIP events around kernel launches: all kernels, or only the
         kernel named `only`."""

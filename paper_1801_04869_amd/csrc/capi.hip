@@ -195,17 +195,21 @@ __global__ void __launch_bounds__(256) finalize_stop_k(const double *__restrict_
     const double r = s * v.inv_nout;
     v.r = r;
     v.iters += 1;
-    if (!isfinite(r)) v.done = 2;
-    else if (v.fixed > 0) v.done = v.iters >= v.fixed ? 1 : 0;
+    if (!isfinite(r)) {
+      v.done = 2;
+      v.fail = 1;
+    } else if (v.fixed > 0) v.done = v.iters >= v.fixed ? 1 : 0;
     else v.done = r < v.thr ? 1 : 0;
     *it = v;
     *mirror = v;
   }
 }
 
-// Reset of the iteration state at the start of a right-hand side.
-__global__ void __launch_bounds__(64) iter_init_k(IterState *it, IterState *mirror, IterState v) {
+// Reset of the iteration state at the start of a right-hand side; keep_fail
+// carries the failure flag of the evaluations queued before it.
+__global__ void __launch_bounds__(64) iter_init_k(IterState *it, IterState *mirror, IterState v, int keep_fail) {
   if (threadIdx.x == 0) {
+    if (keep_fail) v.fail = it->fail;
     *it = v;
     *mirror = v;
   }
@@ -316,7 +320,8 @@ int run_finalize_stop(mag_ctx *c, int nparts) {
 
 int run_iter_init(mag_ctx *c, const IterState &is) {
   ProfScope ps(c, K_FINALIZE);
-  hipLaunchKernelGGL(iter_init_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->h_it, is);
+  // an evaluation queued behind an unchecked asynchronous one keeps its failure flag
+  hipLaunchKernelGGL(iter_init_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->h_it, is, c->async_pending ? 1 : 0);
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
@@ -578,7 +583,14 @@ static int ready(mag_ctx *c) {
 
 static int rhs_impl(mag_ctx *c, const double *state, double t, double *out, int *n_inner) {
   if (!c->warm_enabled) c->warm_valid = false;
-  return c->dim == 3 ? bulk_rhs(c, state, t, out, n_inner) : film_rhs(c, state, t, out, n_inner);
+  int it = 0;
+  const int rc = c->dim == 3 ? bulk_rhs(c, state, t, out, &it) : film_rhs(c, state, t, out, &it);
+  if (rc >= 0) {
+    c->stat_rhs += 1;
+    c->stat_inner += it;
+  }
+  if (n_inner) *n_inner = it;
+  return rc;
 }
 
 static int rhs_vjp_impl(mag_ctx *c, const double *state, double t, const double *out_bar, double *state_bar,
@@ -607,7 +619,7 @@ int mag_rhs_status(mag_ctx *c, int *n_inner) {
   if (n_inner) *n_inner = c->h_it->iters;
   if (!c->async_pending) return MAG_OK;
   c->async_pending = false;
-  if (c->h_it->done == 2 || !std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C)) {
+  if (c->h_it->fail || c->h_it->done == 2 || !std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C)) {
     c->warm_valid = false;
     return set_error(c, MAG_E_NUMERIC, "non-finite residual");
   }
@@ -657,9 +669,10 @@ static int launch_axpy(mag_ctx *c, double *out, const double *y, const double *k
 
 // Stage evaluations k2..k4 of a step with a fixed inner count (film) are
 // enqueued without a host wait: nothing in them is data-dependent control.
-// The step's one synchronisation then checks the state of the last
-// evaluation, which a non-finite value in any stage reaches through the stage
-// states.  With the stop test every evaluation keeps its host poll.
+// A stage whose residual turns non-finite stops writing its output, so the
+// failure flag of the iteration state is sticky along the queued stages (the
+// reset of each later stage keeps it) and the step's one synchronisation
+// checks it.  With the stop test every evaluation keeps its host poll.
 static int stage_rhs(mag_ctx *c, const double *y, double t, double *k) {
   c->rhs_async = c->fixed_iters > 0 && c->dim == 2;
   const int rc = rhs_impl(c, y, t, k, nullptr);
@@ -671,7 +684,7 @@ static int stage_rhs(mag_ctx *c, const double *y, double t, double *k) {
 static int stages_status(mag_ctx *c) {
   if (!c->async_pending) return MAG_OK;
   c->async_pending = false;
-  if (c->h_it->done == 2 || !std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C)) {
+  if (c->h_it->fail || c->h_it->done == 2 || !std::isfinite(c->h_it->r) || !std::isfinite(c->h_it->C)) {
     c->warm_valid = false;
     return set_error(c, MAG_E_NUMERIC, "non-finite residual");
   }
@@ -913,6 +926,14 @@ int mag_rhs_vjp(mag_ctx *c, const double *state, double t, const double *out_bar
   if (rc) return rc;
   if (!state || !out_bar || !state_bar) return set_error(c, MAG_E_ARG, "NULL argument");
   return rhs_vjp_impl(c, state, t, out_bar, state_bar, jc_bar);
+}
+
+int mag_stats(mag_ctx *c, int reset, long long *n_rhs, long long *n_inner) {
+  if (!c) return MAG_E_ARG;
+  if (n_rhs) *n_rhs = c->stat_rhs;
+  if (n_inner) *n_inner = c->stat_inner;
+  if (reset) c->stat_rhs = c->stat_inner = 0;
+  return MAG_OK;
 }
 
 int mag_prof_enable(mag_ctx *c, int on) {

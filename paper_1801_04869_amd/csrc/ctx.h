@@ -19,7 +19,8 @@ struct IterState {
   int done;       // 1 once the stop test passed (or the fixed count is reached)
   int iters;      // inner iterations performed (film: evaluations of (11))
   int fixed;      // fixed iteration count, 0 = stop test
-  int pad;
+  int fail;       // sticky: set with done = 2; kept by the reset that starts an
+                  // evaluation queued behind an unchecked asynchronous one
   double thr;     // stop threshold tol * max(|dh_e/dt|, 1)
   double inv_nout;
   double C;       // film: free-space mean of G, eq. (11)
@@ -133,6 +134,7 @@ struct mag_ctx {
   std::vector<mag::ProfRec> prof;
   std::vector<hipEvent_t> ev_pool;
   int cur_iter = -1;
+  long long stat_rhs = 0, stat_inner = 0;   // mag_stats counts
   double prof_ms[mag::K_COUNT] = {0};
   int prof_cnt[mag::K_COUNT] = {0};
 };

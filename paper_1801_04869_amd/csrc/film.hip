@@ -863,6 +863,7 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
       it->r = r;
       it->iters = iters;
       it->done = done;
+      if (done == 2) it->fail = 1;
       *mirror = *it;
     }
     if (done) return;
@@ -1396,6 +1397,7 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
       c->async_pending = true;
       c->last_iters = kmax;
       c->warm_valid = true;
+      if (n_inner) *n_inner = kmax;
       return MAG_OK;
     }
     MAG_HIP(c, hipStreamSynchronize(c->stream));

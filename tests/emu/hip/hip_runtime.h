@@ -23,6 +23,7 @@
 #include <sanitizer/asan_interface.h>
 
 #include <barrier>
+#include <condition_variable>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -349,6 +350,63 @@ inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) { *ms = 0; return hipSuccess; }
 
+namespace emu {
+// Persistent work-item threads, reused by every launch (a fresh thread per
+// work-item would exhaust the sanitizer's thread registry on long runs).
+// run(n, f) executes f(0..n-1) on the first n workers and waits for them.
+struct Pool {
+  std::vector<std::thread> th;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::function<void(unsigned)> job;
+  unsigned njob = 0, remaining = 0;
+  unsigned long long gen = 0;
+  bool stop = false;
+  void worker(unsigned i) {
+    unsigned long long seen = 0;
+    for (;;) {
+      std::function<void(unsigned)> f;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stop || gen != seen; });
+        if (stop) return;
+        seen = gen;
+        if (i >= njob) continue;
+        f = job;
+      }
+      f(i);
+      std::lock_guard<std::mutex> lk(mu);
+      if (--remaining == 0) done_cv.notify_all();
+    }
+  }
+  void run(unsigned n, std::function<void(unsigned)> f) {
+    while (th.size() < n) {
+      const unsigned i = (unsigned)th.size();
+      th.emplace_back([this, i] { worker(i); });
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    job = std::move(f);
+    njob = n;
+    remaining = n;
+    ++gen;
+    cv.notify_all();
+    done_cv.wait(lk, [&] { return remaining == 0; });
+  }
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto &t : th) t.join();
+  }
+};
+inline Pool &pool() {
+  static Pool p;
+  return p;
+}
+}  // namespace emu
+
 template <typename... KA, typename... A>
 void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t shm, A... args) {
   const unsigned nt = b.x * b.y * b.z;
@@ -383,16 +441,12 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t shm, A... args) {
         emu::bar = &br;
         std::vector<double> xb(((nt + 63) / 64) * 64, 0.0);
         emu::xbuf = &xb;
-        std::vector<std::thread> th;
-        th.reserve(nt);
-        for (unsigned t = 0; t < nt; ++t)
-          th.emplace_back([&, t]() {
-            emu::tIdx = dim3(t % b.x, (t / b.x) % b.y, t / (b.x * b.y));
-            emu::bIdx = dim3(bx, by, bz);
-            std::apply(k, conv);
-            br.arrive_and_drop();
-          });
-        for (auto &x : th) x.join();
+        emu::pool().run(nt, [&](unsigned t) {
+          emu::tIdx = dim3(t % b.x, (t / b.x) % b.y, t / (b.x * b.y));
+          emu::bIdx = dim3(bx, by, bz);
+          std::apply(k, conv);
+          br.arrive_and_drop();
+        });
         std::free(d);
       }
   emu::poison_device(true);

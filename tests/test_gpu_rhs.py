@@ -172,7 +172,10 @@ def test_film_rhs_converged_sequence(prec):
             assert it == rit
             assert rel_l2(out, ref) < TOL[prec]
         else:
+            # the mixed form may stop one evaluation earlier or later; its
+            # result is then within the stop tolerance of the oracle's
             assert abs(it - rit) <= 1
+            assert rel_l2(out, ref) < (TOL[prec] if it == rit else 10 * prob.tol)
 
 
 def test_film_observables():
@@ -470,3 +473,27 @@ def test_film_async_fixed_count_matches_synchronous():
     with pytest.raises(api.MagError) as e:
         ctx.rhs_status()
     assert e.value.code == api.E_NUMERIC
+
+
+def test_film_async_failure_is_sticky_until_checked():
+    """A queued fixed-count evaluation whose residual turns non-finite stops
+    writing its output; a good evaluation queued behind it must not hide the
+    failure: mag_rhs_status reports E_NUMERIC for the pair, and the next pair
+    of good evaluations reports OK."""
+    case = film_case(64, 64, kind="rect", n=19.0)
+    ctx = make_gpu(case, api.FP64, fixed=2)
+    s = torch.from_numpy(case["state"]).cuda()
+    bad = case["state"].copy()
+    q, p = np.argwhere(make_oracle(case).in_node)[0]
+    bad[q, p] = np.nan
+    sb = torch.from_numpy(bad).cuda()
+    o = torch.empty_like(s)
+    ctx.rhs(sb, 0.1, o, wait=False)
+    ctx.rhs(s, 0.1, o, wait=False)
+    with pytest.raises(api.MagError) as e:
+        ctx.rhs_status()
+    assert e.value.code == api.E_NUMERIC
+    ctx.rhs(s, 0.1, o, wait=False)
+    ctx.rhs(s, 0.1, o, wait=False)
+    st, it = ctx.rhs_status()
+    assert st == 0 and it == 2 and torch.isfinite(o).all()
