@@ -230,6 +230,23 @@ int mag_prof_enable(mag_ctx *ctx, int on);
 int mag_prof_read(mag_ctx *ctx, int id, int *count, double *total_ms);
 const char *mag_prof_kernel_name(int id);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the film
+ * magnetic moment of mag_observe, m = (0, 0, sum of g dx dy) with
+ * dx = 2 Lx / nx, dy = 2 Ly / ny, without a context and without allocating.
+ * g: device FP64 stream function [ny][nx]; m: device, 3 doubles, written
+ * (no host copy, no synchronisation); hip_stream: the stream to enqueue on
+ * (NULL = the default stream).  Per-block partial sums live in a library
+ * array of MAG_NOALLOC_MAX_PARTS doubles on each device (held until the
+ * process ends), so nx * ny must not exceed MAG_NOALLOC_MAX_PARTS * 2048
+ * nodes (MAG_E_ARG otherwise, nothing enqueued).  Every call on a device
+ * uses the same array: calls that overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller.  The array's device
+ * address is looked up by mag_create, or by the first call on a device.
+ * Returns MAG_OK, MAG_E_ARG or MAG_E_HIP. */
+#define MAG_NOALLOC_MAX_PARTS 8192
+int mag_film_moment_noalloc(const double *g, int nx, int ny, double Lx, double Ly, double *m, void *hip_stream);
+
 /* Counts of the work done since the last reset: *n_rhs right-hand sides
  * evaluated (mag_rhs and the stages of mag_step / mag_integrate /
  * mag_step_fixed) and *n_inner inner iterations (evaluations of (11) in 2D,

@@ -40,6 +40,7 @@ SIGNATURES = {
     "mag_prof_enable": (c_int, [c_void_p, c_int]),
     "mag_prof_read": (c_int, [c_void_p, c_int, P_int, P_double]),
     "mag_prof_kernel_name": (ctypes.c_char_p, [c_int]),
+    "mag_film_moment_noalloc": (c_int, [c_void_p, c_int, c_int, c_double, c_double, c_void_p, c_void_p]),
     "mag_stats": (c_int, [c_void_p, c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
 }
 

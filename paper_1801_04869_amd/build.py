@@ -25,8 +25,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-ato
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-Wno-unused-result", "-Wno-unknown-pragmas"]
 
-SOURCES = ["capi.hip", "film.hip", "bulk.hip"]
-CONTRACT = {"capi.hip": "-ffp-contract=off", "film.hip": "-ffp-contract=fast", "bulk.hip": "-ffp-contract=fast"}
+SOURCES = ["capi.hip", "film.hip", "bulk.hip", "noalloc.hip"]
+CONTRACT = {"capi.hip": "-ffp-contract=off", "film.hip": "-ffp-contract=fast", "bulk.hip": "-ffp-contract=fast",
+            "noalloc.hip": "-ffp-contract=off"}
 
 
 def _compile(src):

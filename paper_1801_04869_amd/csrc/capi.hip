@@ -398,6 +398,9 @@ int mag_create(mag_ctx **out, int dim, int precision, void *hip_stream) {
     delete c;
     return MAG_E_NOMEM;
   }
+  // set-up of the allocation-free entry point on this device (retried by
+  // its first call if it fails here)
+  (void)noalloc_setup();
   *out = c;
   return MAG_OK;
 }

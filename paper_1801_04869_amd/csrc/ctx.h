@@ -206,5 +206,6 @@ int run_iter_init(mag_ctx *c, const IterState &is);
 // the partial sums start at d_part + first.
 int run_finalize_mean(mag_ctx *c, int nparts, int which, int first = 0);
 int run_to_double(mag_ctx *c, const void *src, double *dst, long long n);
+int noalloc_setup();   // noalloc.hip: the current device's scratch address
 
 }  // namespace mag

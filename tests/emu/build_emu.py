@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "_build", "libmagfft_emu.so")
 
 def build(asan=True):
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
-    srcs = [os.path.join(CSRC, s) for s in ("capi.hip", "film.hip", "bulk.hip")]
+    srcs = [os.path.join(CSRC, s) for s in ("capi.hip", "film.hip", "bulk.hip", "noalloc.hip")]
     newest = max(os.path.getmtime(p) for p in srcs + [os.path.join(HERE, "hip", "hip_runtime.h")] +
                  [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")])
     if os.path.exists(OUT) and os.path.getmtime(OUT) > newest:

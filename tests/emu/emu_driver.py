@@ -155,6 +155,15 @@ def main(path, which):
         jj = Dev(np.zeros(case["dim"] * nn))
         rc = L.mag_observe(h, P(s), 0.3, P(hz), P(jj), m)
         print("   observe rc=%d m=%s" % (rc, list(m)), flush=True)
+        if case["dim"] == 2:
+            # the allocation-free moment against mag_observe's
+            md = Dev(np.full(3, np.nan))
+            nx, ny, _ = case["n"]
+            rc2 = L.mag_film_moment_noalloc(P(s), nx, ny, case["L"][0], case["L"][1], P(md), None)
+            mn = md.numpy()
+            okm = rc2 == 0 and mn[0] == 0 and mn[1] == 0 and abs(mn[2] - m[2]) <= 1e-13 * max(abs(m[2]), 1e-300)
+            fails += not okm
+            print("   noalloc moment rc=%d m=%s %s" % (rc2, list(mn), "ok" if okm else "FAIL"), flush=True)
         L.mag_destroy(h)
     print("EMU_DONE fails=%d" % fails, flush=True)
     return fails

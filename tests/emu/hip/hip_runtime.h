@@ -343,6 +343,24 @@ inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) {
   return hipSuccess;
 }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipGetDevice(int *d) {
+  *d = 0;
+  return hipSuccess;
+}
+// A `__device__` array is a host static here: its address is registered as
+// device memory (poisoned for host code) the first time it is looked up.
+#define HIP_SYMBOL(x) (x)
+template <typename T>
+inline hipError_t hipGetSymbolAddress(void **p, T &sym) {
+  uintptr_t b = 0;
+  size_t l = 0;
+  if (emu::kind_of(&sym, &b, &l) != emu::DEVICE) {
+    emu::reg()[reinterpret_cast<uintptr_t>(&sym)] = emu::Alloc{sizeof(T), emu::DEVICE};
+    ASAN_POISON_MEMORY_REGION(&sym, sizeof(T));
+  }
+  *p = &sym;
+  return hipSuccess;
+}
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline const char *hipGetErrorString(hipError_t) { return "emu"; }
 inline hipError_t hipEventCreate(hipEvent_t *e) { *e = nullptr; return 1; }

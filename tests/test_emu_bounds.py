@@ -56,6 +56,6 @@ def test_emulated_kernels_in_bounds_and_match_oracle(which, tmp_path):
         return
     from tests.emu import kernel_limits
     seen, problems = kernel_limits.check(lib, log, os.path.join(ROOT, "paper_1801_04869_amd", "csrc"),
-                                         ["capi.hip", "film.hip", "bulk.hip"])
+                                         ["capi.hip", "film.hip", "bulk.hip", "noalloc.hip"])
     assert seen
     assert not problems, problems
