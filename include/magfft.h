@@ -163,6 +163,29 @@ int mag_step(mag_ctx *ctx, double *state, double *t, double *dt, double rtol, do
 int mag_integrate(mag_ctx *ctx, double *state, double t0, double t1, double rtol, double atol,
                   double *obs, int obs_cap, int *n_steps);
 
+/* mag_integrate with the step control on the device (Sec. 2.2: the adaptive
+ * Bogacki-Shampine pair of ode23 around the right-hand side), for a film
+ * with a fixed inner count (mag_set_solver fixed_iters > 0; MAG_E_STATE
+ * otherwise).  After the first right-hand side and the first step size (as
+ * mag_integrate), t and dt live in device memory: each step attempt (three
+ * stage right-hand sides, the stage sums, the error norm, accept / reject
+ * with the controller of mag_step, the end-time clip and the commit of the
+ * accepted state) is a fixed sequence of kernels with no host decision.
+ * `chunk` attempts are captured once into a HIP graph on a stream of the
+ * library's own (ordered after the context's stream by events) and the
+ * graph is replayed until t1 is reached or max_attempts attempts have run,
+ * with one host synchronisation per replay.  The instantiated graph is kept
+ * and reused while the state buffer, the chunk and every set-up call stay
+ * the same.  A stage whose residual turns non-finite rejects the attempt
+ * with dt / 2 and the next attempt restarts its free-space iteration from
+ * dh_e/dt.  state: device FP64, advanced in place (its last accepted value).
+ * n_accepted, n_rejected, t_reached: host, nullable.  Returns MAG_OK when t1
+ * is reached, MAG_STEP_UNDERFLOW if the step collapses, MAG_NOT_CONVERGED if
+ * max_attempts ran out first.  1 <= chunk <= 256. */
+int mag_integrate_captured(mag_ctx *ctx, double *state, double t0, double t1, double rtol, double atol,
+                           int chunk, long long max_attempts, int *n_accepted, int *n_rejected,
+                           double *t_reached);
+
 /* Observables of a state (post-processing, Sec. 2.1 last formula):
  * 2D: hz (device, nx*ny, nodes) = h_e + F^{-1}[|k|/2 F(g)]; j (device,
  *     2*nx*ny: j_x on x-edges then j_y on y-edges, eq. (2)); m[0..2] (host)

@@ -31,7 +31,7 @@ import numpy as np
 
 from .field import AppliedField
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, NOT_FINITE = 0, 1, 2
 X, Y, Z = 2, 1, 0          # array axis of each coordinate
 
 
@@ -212,6 +212,10 @@ def rhs(prob, h, t):
         H = Hn
         stop = (i == kmax - 1) if fixed else (r < thr)
         if stop:
+            if not np.isfinite(r):
+                # a failed evaluation: no warm start for the next call (Sec. 2.2)
+                prob.warm = None
+                return None, i + 1, NOT_FINITE
             prob.warm = H.copy()
             return H, i + 1, OK
     prob.warm = None

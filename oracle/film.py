@@ -36,7 +36,7 @@ import numpy as np
 
 from .field import AppliedField
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, NOT_FINITE = 0, 1, 2
 
 
 def paper_sigma(dx, dy):
@@ -168,7 +168,8 @@ def rhs(prob, g, t):
     ``fixed_iters`` > 0 exactly that many evaluations of (11) are done and the
     last one is returned without a stop test.  Failure to converge within
     ``max_inner`` evaluations returns status NOT_CONVERGED and clears the
-    warm start (Sec. 2.2: the integrator then shrinks its step).
+    warm start (Sec. 2.2: the integrator then shrinks its step); so does a
+    fixed-count evaluation whose residual is not finite (status NOT_FINITE).
     """
     hde = float(prob.field.hdot(t)[2])
     out = prob.out_node
@@ -187,6 +188,11 @@ def rhs(prob, g, t):
         r = np.abs(gdot[out]).mean()
         stop = (i == kmax - 1) if fixed else (r < thr)
         if stop:
+            if not np.isfinite(r):
+                # a failed evaluation (overflow in a stage): the integrator
+                # cuts the step (Sec. 2.2) and the next call starts cold
+                prob.warm = None
+                return None, i + 1, NOT_FINITE
             prob.warm = H.copy()
             return gdot, i + 1, OK
         U = np.where(out, gdot, 0.0)                         # gdot_out of (12)

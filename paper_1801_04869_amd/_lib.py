@@ -29,6 +29,8 @@ SIGNATURES = {
     "mag_rhs_status": (c_int, [c_void_p, P_int]),
     "mag_step": (c_int, [c_void_p, c_void_p, P_double, P_double, c_double, c_double, P_int]),
     "mag_integrate": (c_int, [c_void_p, c_void_p, c_double, c_double, c_double, c_double, P_double, c_int, P_int]),
+    "mag_integrate_captured": (c_int, [c_void_p, c_void_p, c_double, c_double, c_double, c_double, c_int,
+                                       ctypes.c_longlong, P_int, P_int, P_double]),
     "mag_observe": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, P_double]),
     "mag_rhs_vjp": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "mag_reset_warm_start": (c_int, [c_void_p]),

@@ -128,6 +128,19 @@ class Context:
                 rows.append(tuple(obs[6 * i:6 * i + 6]))
         return ns.value, rows
 
+    def integrate_captured(self, state, t0, t1, rtol=1e-3, atol=1e-6, chunk=16, max_attempts=10 ** 7):
+        """Integrate in place with the step control on the device, step
+        attempts replayed from a captured graph (film, fixed inner count);
+        returns (accepted, rejected, t reached); t reached < t1 when
+        max_attempts ran out first."""
+        na, nr, tr = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+        rc = self._L.mag_integrate_captured(self._h, _ptr(state, torch.float64), float(t0), float(t1), rtol, atol,
+                                            int(chunk), int(max_attempts), ctypes.byref(na), ctypes.byref(nr),
+                                            ctypes.byref(tr))
+        # NOT_CONVERGED here means max_attempts ran out before t1
+        self._check(rc, allow=(OK, NOT_CONVERGED))
+        return na.value, nr.value, tr.value
+
     def observe(self, state, t, want_hz=True, want_j=True):
         """Returns (hz, j, m): hz on nodes (2D) / z-edges (3D), j on edges/faces
         (2 or 3 component planes), m the magnetic moment (host tuple)."""

@@ -293,6 +293,146 @@ __global__ void __launch_bounds__(256) rk_ratio_k(const double *__restrict__ f, 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// ---------------------------------------------------------------- device-side step control
+// Kernels of a step attempt whose t and h live in device memory (StepCtl):
+// the same arithmetic as the host-driven step (stage times t + c h, stage
+// states y + (a h) k, error norm, controller), so that a run of attempts can
+// be captured in one graph and replayed without host decisions.  Every kernel
+// returns at once when the run is finished.
+
+__device__ __forceinline__ double field_hdot_z(const FieldZ &f, double t) {
+  if (f.kind == MAG_FIELD_RAMP) return f.dz * f.rate;
+  if (f.kind == MAG_FIELD_SINE) return f.dz * (f.amp * f.omega * cos(f.omega * t));
+  return 0.0;   // the rotating field lies in the film plane
+}
+
+// Iteration state of the stage at t + cs h: dh_e/dt there, the stop threshold
+// tol max(|dh_e/dt|, 1), the failure flag kept from the earlier stages of the
+// attempt (keep_fail), done when the run is finished.
+__global__ void __launch_bounds__(64) stage_init_k(IterState *it, IterState *mirror, const StepCtl *sc, FieldZ f,
+                                                   double cs, IterState base, double tol, int keep_fail) {
+  if (threadIdx.x != 0) return;
+  IterState v = base;
+  // the first stage of an attempt after a failed one restarts cold (as the
+  // host-driven step drops its warm start after a failure)
+  if (keep_fail) v.fail = it->fail;
+  else v.cold = it->fail;
+  const double ts = sc->t + cs * sc->h;
+  const double hde = field_hdot_z(f, ts);
+  v.hde = hde;
+  v.thr = tol * (fabs(hde) > 1.0 ? fabs(hde) : 1.0);
+  if (sc->finished) v.done = 1;
+  *it = v;
+  *mirror = v;
+}
+
+// out = y + (hfac h) sum_i w_i k_i  (nk <= 3), h from the step record.
+__global__ void __launch_bounds__(256) rk_axpy_sc_k(double *__restrict__ out, const double *__restrict__ y,
+                                                    const double *__restrict__ k0, const double *__restrict__ k1,
+                                                    const double *__restrict__ k2, double w0, double w1, double w2,
+                                                    int nk, double hfac, const StepCtl *__restrict__ sc,
+                                                    long long n) {
+  if (sc->finished) return;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double h = hfac * sc->h;
+  double s = w0 * k0[i];
+  if (nk > 1) s += w1 * k1[i];
+  if (nk > 2) s += w2 * k2[i];
+  out[i] = y[i] + h * s;
+}
+
+// Per-block max of the scaled error (as rk_errnorm_k), h, rtol and atol from the step record.
+__global__ void __launch_bounds__(256) rk_errnorm_sc_k(const double *__restrict__ k1, const double *__restrict__ k2,
+                                                       const double *__restrict__ k3, const double *__restrict__ k4,
+                                                       double e1, double e2, double e3, double e4,
+                                                       const double *__restrict__ y, const double *__restrict__ yn,
+                                                       const StepCtl *__restrict__ sc, long long n,
+                                                       double *__restrict__ part) {
+  __shared__ double sh[256];
+  if (sc->finished) return;
+  const double h = sc->h, rtol = sc->rtol, atol = sc->atol;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double err = h * (e1 * k1[i] + e2 * k2[i] + e3 * k3[i] + e4 * k4[i]);
+    const double sc_ = fmax(rtol * fmax(fabs(y[i]), fabs(yn[i])), atol);
+    v = fabs(err) / sc_;
+    if (!isfinite(v)) v = INFINITY;
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Accept or reject the attempt: error norm = max of the block maxima; a
+// failed stage (non-finite residual, sticky flag) rejects with h / 2 (the
+// paper's "huge gdot" device, Sec. 2.2); otherwise the controller of the
+// host-driven step.  Then the end-time clip and the underflow check that the
+// host loop applies before an attempt.
+__global__ void __launch_bounds__(256) step_accept_k(StepCtl *sc, StepCtl *mirror, const double *__restrict__ part,
+                                                     int nb, const IterState *__restrict__ it) {
+  __shared__ double sh[256];
+  if (sc->finished) {
+    if (threadIdx.x == 0) {
+      sc->commit = 0;
+      *mirror = *sc;
+    }
+    return;
+  }
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) m = fmax(m, part[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  StepCtl v = *sc;
+  const double en = sh[0];
+  const double h = v.h;
+  v.err = en;
+  if (it->fail == 0 && en <= 1.0) {
+    v.t = v.t + h;
+    const double fac = en == 0.0 ? 5.0 : fmin(5.0, fmax(0.2, 0.8 * pow(en, -1.0 / 3.0)));
+    v.h = h * fac;
+    v.accepted += 1;
+    v.commit = 1;
+  } else {
+    const double fac = it->fail ? 0.5 : fmax(0.2, 0.8 * pow(en, -1.0 / 3.0));
+    v.h = h * fac;
+    v.rejected += 1;
+    v.commit = 0;
+  }
+  if (!(v.t < v.t_end)) {
+    v.finished = 1;
+  } else {
+    if (1.1 * v.h >= v.t_end - v.t) v.h = v.t_end - v.t;
+    if (v.h <= 16.0 * 2.220446049250313e-16 * fmax(fabs(v.t), 1.0)) {
+      v.status = MAG_STEP_UNDERFLOW;
+      v.finished = 1;
+    }
+  }
+  *sc = v;
+  *mirror = v;
+}
+
+// An accepted attempt: y <- y_new and k1 <- k4 (first same as last).
+__global__ void __launch_bounds__(256) step_commit_k(double *__restrict__ y, const double *__restrict__ yn,
+                                                     double *__restrict__ k1, const double *__restrict__ k4,
+                                                     const StepCtl *__restrict__ sc, long long n) {
+  if (!sc->commit) return;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  y[i] = yn[i];
+  k1[i] = k4[i];
+}
+
 template <typename T>
 __global__ void fill_twiddles(cx<T> *dst, const double *src, long long n) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -405,9 +545,22 @@ int mag_create(mag_ctx **out, int dim, int precision, void *hip_stream) {
   return MAG_OK;
 }
 
+static void release_capture(mag_ctx *c) {
+  if (c->cap_stream) (void)hipStreamSynchronize(c->cap_stream);
+  if (c->cap_exec) (void)hipGraphExecDestroy(c->cap_exec);
+  c->cap_exec = nullptr;
+  c->cap_state = nullptr;
+}
+
 void mag_destroy(mag_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  release_capture(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (hipEvent_t e : c->cap_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->d_sc) (void)hipFree(c->d_sc);
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
   prof_clear(c);
   for (hipEvent_t e : c->ev_pool)
     if (e) (void)hipEventDestroy(e);
@@ -426,6 +579,7 @@ const char *mag_last_error(const mag_ctx *c) { return c ? c->err.c_str() : "null
 
 int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, double Lz) {
   CHECK_CTX(c);
+  ++c->gen;   // a captured step graph bakes the set-up in
   if (!pow2_in(nx, 16, 2048) || !pow2_in(ny, 16, 2048))
     return set_error(c, MAG_E_ARG, "nx, ny must be powers of two in [16, 2048]");
   if (c->dim == 2 && nz != 1) return set_error(c, MAG_E_ARG, "nz must be 1 for a film");
@@ -436,6 +590,7 @@ int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, doubl
                      "the 3D path is disabled (held off the GPU after an unexplained memory fault; "
                      "MAG_BULK_ENABLE compiles it in)");
   MAG_HIP(c, hipStreamSynchronize(c->stream));
+  release_capture(c);
   IterState *keep_it = c->d_it;
   c->d_it = nullptr;
   free_all(c);
@@ -498,6 +653,7 @@ int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, doubl
 
 int mag_set_domain(mag_ctx *c, const uint8_t *material) {
   CHECK_CTX(c);
+  ++c->gen;   // a captured step graph bakes the set-up in
   if (!c->grid_set) return set_error(c, MAG_E_STATE, "mag_set_domain before mag_set_grid");
   if (!material) return set_error(c, MAG_E_ARG, "material is NULL");
   std::vector<uint8_t> m(c->nnode);
@@ -518,6 +674,7 @@ int mag_set_domain(mag_ctx *c, const uint8_t *material) {
 
 int mag_set_params(mag_ctx *c, const double *jc_map, double jc0, double n, double e0, double rho_out) {
   CHECK_CTX(c);
+  ++c->gen;   // a captured step graph bakes the set-up in
   if (!c->grid_set) return set_error(c, MAG_E_STATE, "mag_set_params before mag_set_grid");
   if (!(n >= 1.0) || !(jc0 > 0) || !(e0 > 0) || !(rho_out >= 0) || !std::isfinite(n) || !std::isfinite(jc0))
     return set_error(c, MAG_E_ARG, "need n >= 1, jc0 > 0, e0 > 0, rho_out >= 0");
@@ -553,6 +710,7 @@ int mag_set_params(mag_ctx *c, const double *jc_map, double jc0, double n, doubl
 
 int mag_set_solver(mag_ctx *c, double lambda, double inner_tol, int max_inner, int fixed_iters) {
   CHECK_CTX(c);
+  ++c->gen;   // a captured step graph bakes the set-up in
   if (!(lambda > 0) || !(inner_tol >= 0) || max_inner < 1 || fixed_iters < 0 || max_inner > 100000 ||
       fixed_iters > 100000)
     return set_error(c, MAG_E_ARG, "need lambda > 0, inner_tol >= 0, 1 <= max_inner, fixed_iters >= 0");
@@ -566,6 +724,7 @@ int mag_set_solver(mag_ctx *c, double lambda, double inner_tol, int max_inner, i
 
 int mag_set_field(mag_ctx *c, int kind, const double dir[3], double amp, double omega, double rate) {
   CHECK_CTX(c);
+  ++c->gen;   // a captured step graph bakes the set-up in
   if (kind < 0 || kind > 2) return set_error(c, MAG_E_ARG, "unknown field kind");
   if ((kind != MAG_FIELD_ROTATE) && !dir) return set_error(c, MAG_E_ARG, "dir is NULL");
   c->fkind = kind;
@@ -911,6 +1070,173 @@ int mag_integrate(mag_ctx *c, double *state, double t0, double t1, double rtol, 
       ++*n_steps;
     }
   }
+  return MAG_OK;
+}
+
+// ---------------------------------------------------------------- device-driven integration
+static int ensure_capture(mag_ctx *c) {
+  if (!c->d_sc) MAG_HIP(c, hipMalloc(&c->d_sc, sizeof(StepCtl)));
+  if (!c->h_sc) MAG_HIP(c, hipHostMalloc(&c->h_sc, sizeof(StepCtl), hipHostMallocCoherent));
+  // a stream of the library's own (default priority): capture needs one that
+  // is not the legacy default stream
+  if (!c->cap_stream) MAG_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  for (hipEvent_t &e : c->cap_ev)
+    if (!e) MAG_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return MAG_OK;
+}
+
+// One step attempt of the device-driven integration, enqueued on c->stream:
+// the three stage right-hand sides (film, fixed inner count), the stage sums,
+// the error norm, accept / dt and the commit.  Buffers: k1..k4 = 0..3,
+// y_stage = 4, y_new = 5.
+static int enqueue_attempt(mag_ctx *c, double *state) {
+  const long long n = state_len(c);
+  double *k1 = rk_buf(c, 0), *k2 = rk_buf(c, 1), *k3 = rk_buf(c, 2), *k4 = rk_buf(c, 3);
+  double *yt = rk_buf(c, 4), *yn = rk_buf(c, 5);
+  const unsigned nbe = (unsigned)((n + 255) / 256);
+  FieldZ f;
+  f.kind = c->fkind;
+  f.dz = c->fdir[2];
+  f.amp = c->famp;
+  f.omega = c->fomega;
+  f.rate = c->frate;
+  IterState base{};
+  base.fixed = c->fixed_iters;
+  base.inv_nout = c->nout > 0 ? 1.0 / (double)c->nout : 0.0;
+  struct Stage {
+    double cs;
+    const double *k0, *k1, *k2;
+    double w0, w1, w2, hfac;
+    int nk;
+    double *y, *k;
+  };
+  const Stage st[3] = {{kRkC2, k1, k1, k1, 1.0, 0.0, 0.0, kA21, 1, yt, k2},
+                       {kRkC3, k2, k2, k2, 1.0, 0.0, 0.0, kA32, 1, yt, k3},
+                       {1.0, k1, k2, k3, kB1, kB2, kB3, 1.0, 3, yn, k4}};
+  for (int s = 0; s < 3; ++s) {
+    {
+      ProfScope ps(c, K_RK);
+      hipLaunchKernelGGL(rk_axpy_sc_k, dim3(nbe), dim3(256), 0, c->stream, st[s].y, state, st[s].k0, st[s].k1,
+                         st[s].k2, st[s].w0, st[s].w1, st[s].w2, st[s].nk, st[s].hfac, c->d_sc, n);
+      hipLaunchKernelGGL(stage_init_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->h_it, c->d_sc, f, st[s].cs, base,
+                         c->tol, s > 0 ? 1 : 0);
+    }
+    if (int rc = film_rhs_enqueue(c, st[s].y, st[s].k)) return rc;
+  }
+  ProfScope ps(c, K_RK);
+  hipLaunchKernelGGL(rk_errnorm_sc_k, dim3(nbe), dim3(256), 0, c->stream, k1, k2, k3, k4, kE1, kE2, kE3, kE4, state,
+                     yn, c->d_sc, n, c->d_red);
+  hipLaunchKernelGGL(step_accept_k, dim3(1), dim3(256), 0, c->stream, c->d_sc, c->h_sc, c->d_red, (int)nbe, c->d_it);
+  hipLaunchKernelGGL(step_commit_k, dim3(nbe), dim3(256), 0, c->stream, state, yn, k1, k4, c->d_sc, n);
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
+int mag_integrate_captured(mag_ctx *c, double *state, double t0, double t1, double rtol, double atol, int chunk,
+                           long long max_attempts, int *n_accepted, int *n_rejected, double *t_reached) {
+  CHECK_CTX(c);
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!state) return set_error(c, MAG_E_ARG, "NULL argument");
+  if (!(t1 > t0) || !(rtol > 0) || !(atol > 0) || !std::isfinite(t0) || !std::isfinite(t1))
+    return set_error(c, MAG_E_ARG, "need finite t1 > t0, rtol > 0, atol > 0");
+  if (chunk < 1 || chunk > 256 || max_attempts < 1) return set_error(c, MAG_E_ARG, "need 1 <= chunk <= 256, max_attempts >= 1");
+  if (c->dim != 2 || c->fixed_iters <= 0)
+    return set_error(c, MAG_E_STATE, "the captured integration needs a film and a fixed inner count");
+  const long long n = state_len(c);
+  if ((rc = ensure_rk(c)) || (rc = ensure_red(c, n)) || (rc = ensure_capture(c))) return rc;
+  // k1 = f(state, t0) and the initial step as in mag_integrate (host driven, synchronising)
+  c->rk_k1 = 0;
+  c->rk_k4 = 3;
+  c->fsal_valid = false;
+  int it0 = 0;
+  rc = rhs_impl(c, state, t0, rk_buf(c, 0), &it0);
+  if (rc) return rc;
+  const int nb = (int)((n + 255) / 256);
+  {
+    ProfScope ps(c, K_RK);
+    hipLaunchKernelGGL(rk_ratio_k, dim3(nb), dim3(256), 0, c->stream, rk_buf(c, 0), state, atol / rtol, n, c->d_red);
+  }
+  MAG_HIP(c, hipGetLastError());
+  double mx = 0.0;
+  if ((rc = host_max(c, nb, &mx))) return rc;
+  const double rh = mx / (0.8 * std::cbrt(rtol));
+  double h = 0.1 * std::fabs(t1 - t0);
+  if (rh * h > 1.0) h = 1.0 / rh;
+  if (1.1 * h >= t1 - t0) h = t1 - t0;
+  StepCtl sc{};
+  sc.t = t0;
+  sc.h = h;
+  sc.t_end = t1;
+  sc.rtol = rtol;
+  sc.atol = atol;
+  *c->h_sc = sc;
+  MAG_HIP(c, hipMemcpyAsync(c->d_sc, c->h_sc, sizeof(StepCtl), hipMemcpyHostToDevice, c->stream));
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  // the graph of `chunk` attempts, captured on the library's stream (rebuilt
+  // when the state buffer, the chunk or any set-up changed)
+  if (!c->cap_exec || c->cap_state != state || c->cap_chunk != chunk || c->cap_gen != c->gen) {
+    release_capture(c);
+    hipStream_t user = c->stream;
+    const bool prof = c->prof_on, dbg = c->debug_sync;
+    c->prof_on = false;
+    c->debug_sync = false;   // no synchronisation while capturing
+    c->stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    int rc2 = MAG_OK;
+    if (e == hipSuccess) {
+      for (int a = 0; a < chunk && rc2 == MAG_OK; ++a) rc2 = enqueue_attempt(c, state);
+      e = hipStreamEndCapture(c->cap_stream, &g);
+    }
+    c->stream = user;
+    c->prof_on = prof;
+    c->debug_sync = dbg;
+    if (rc2 != MAG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc2;
+    }
+    if (e != hipSuccess) return hip_check(c, e, "stream capture of the step graph");
+    e = hipGraphInstantiate(&c->cap_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->cap_exec = nullptr;
+      return hip_check(c, e, "hipGraphInstantiate");
+    }
+    c->cap_state = state;
+    c->cap_chunk = chunk;
+    c->cap_gen = c->gen;
+  }
+  // replays on the library's stream, ordered after the caller's stream
+  MAG_HIP(c, hipEventRecord(c->cap_ev[0], c->stream));
+  MAG_HIP(c, hipStreamWaitEvent(c->cap_stream, c->cap_ev[0], 0));
+  long long launched = 0;
+  while (launched < max_attempts) {
+    MAG_HIP(c, hipGraphLaunch(c->cap_exec, c->cap_stream));
+    launched += chunk;
+    MAG_HIP(c, hipStreamSynchronize(c->cap_stream));
+    if (c->h_sc->finished) break;
+  }
+  MAG_HIP(c, hipEventRecord(c->cap_ev[1], c->cap_stream));
+  MAG_HIP(c, hipStreamWaitEvent(c->stream, c->cap_ev[1], 0));
+  const StepCtl v = *c->h_sc;
+  if (n_accepted) *n_accepted = v.accepted;
+  if (n_rejected) *n_rejected = v.rejected;
+  if (t_reached) *t_reached = v.t;
+  c->stat_rhs += 3LL * (v.accepted + v.rejected);
+  c->stat_inner += 3LL * (v.accepted + v.rejected) * c->fixed_iters;
+  // buffer 0 holds f(state, t) for the next step (first same as last)
+  c->fsal_valid = true;
+  c->fsal_state = state;
+  c->fsal_t = v.t;
+  c->warm_valid = true;
+  c->async_pending = false;
+  if (c->h_it->fail) {
+    // the last attempt failed a stage and was rejected; the state is the last accepted one
+    c->warm_valid = false;
+  }
+  if (v.status == MAG_STEP_UNDERFLOW) return set_error(c, MAG_STEP_UNDERFLOW, "step size underflow at t = %g", v.t);
+  if (!v.finished) return set_error(c, MAG_NOT_CONVERGED, "t = %g not reached after %lld attempts", v.t, launched);
   return MAG_OK;
 }
 

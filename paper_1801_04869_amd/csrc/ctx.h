@@ -21,12 +21,36 @@ struct IterState {
   int fixed;      // fixed iteration count, 0 = stop test
   int fail;       // sticky: set with done = 2; kept by the reset that starts an
                   // evaluation queued behind an unchecked asynchronous one
+  int cold;       // the stencil starts the free space from dh_e/dt, not from the warm start
+  int pad;
   double thr;     // stop threshold tol * max(|dh_e/dt|, 1)
   double inv_nout;
   double C;       // film: free-space mean of G, eq. (11)
   double A;       // film: pending constant shift of (10)/(12)
   double r;       // last residual
   double sum0;    // scratch
+  double hde;     // dh_e/dt of the right-hand side (film: z component), read by
+                  // the stencil and the iteration passes
+};
+
+// Step control of a device-driven integration (mag_integrate_captured): the
+// kernels of a step attempt read t and h here, the accept kernel updates them
+// and copies the record to a coherent pinned mirror that the host reads.
+struct StepCtl {
+  double t, h, t_end, rtol, atol;
+  double err;      // error norm of the last attempt
+  int accepted;    // attempts accepted since the start of the run
+  int rejected;    // attempts rejected
+  int commit;      // the last attempt was accepted: y <- y_new, k1 <- k4
+  int finished;    // t reached t_end or a status was set: every step kernel returns at once
+  int status;      // 0 or MAG_STEP_UNDERFLOW
+  int pad;
+};
+
+// Applied field of a film (z component) for the device-side stage times.
+struct FieldZ {
+  int kind;
+  double dz, amp, omega, rate;
 };
 
 // Kernel identifiers for the instrumentation.
@@ -135,6 +159,17 @@ struct mag_ctx {
   std::vector<hipEvent_t> ev_pool;
   int cur_iter = -1;
   long long stat_rhs = 0, stat_inner = 0;   // mag_stats counts
+
+  // device-driven integration (mag_integrate_captured)
+  mag::StepCtl *d_sc = nullptr;
+  mag::StepCtl *h_sc = nullptr;   // pinned, coherent
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t cap_ev[2] = {nullptr, nullptr};
+  hipGraphExec_t cap_exec = nullptr;
+  const double *cap_state = nullptr;  // key of the instantiated graph
+  int cap_chunk = 0;
+  unsigned long long cap_gen = 0;
+  unsigned long long gen = 1;         // bumped by every set_* call
   double prof_ms[mag::K_COUNT] = {0};
   int prof_cnt[mag::K_COUNT] = {0};
 };
@@ -177,14 +212,20 @@ struct ProfLaunch {
   hipEvent_t start() const { return r.a; }
   hipEvent_t stop() const { return r.b; }
 };
-#define MAG_TIMED_LAUNCH(pl, K, G, B, S, STREAM, ...) \
-  hipExtLaunchKernelGGL(K, G, B, S, STREAM, (pl).start(), (pl).stop(), 0, __VA_ARGS__)
+#define MAG_TIMED_LAUNCH(pl, K, G, B, S, STREAM, ...)                                   \
+  do {                                                                                  \
+    if ((pl).start())                                                                   \
+      hipExtLaunchKernelGGL(K, G, B, S, STREAM, (pl).start(), (pl).stop(), 0, __VA_ARGS__); \
+    else                                                                                \
+      hipLaunchKernelGGL(K, G, B, S, STREAM, __VA_ARGS__);                               \
+  } while (0)
 
 // dimension-specific drivers
 int film_alloc(mag_ctx *c);
 int film_domain(mag_ctx *c);
 int film_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner);
 int film_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m);
+int film_rhs_enqueue(mag_ctx *c, const double *state, double *out);
 int film_rhs_vjp(mag_ctx *c, const double *state, double t, const double *out_bar,
                  double *state_bar, double *jc_bar);
 int film_hz_transpose(mag_ctx *c, const double *hz_bar, double *state_bar);

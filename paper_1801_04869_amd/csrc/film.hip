@@ -91,9 +91,15 @@ constexpr int kStencilThreads = 1024;
 template <typename T>
 __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) == 4 ? 8 : 4) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
-                                                    T *__restrict__ H, FilmGeom G, FilmLaw law, double hde,
-                                                    int warm, double *__restrict__ part) {
+                                                    T *__restrict__ H, FilmGeom G, FilmLaw law,
+                                                    const IterState *__restrict__ it, int warm,
+                                                    double *__restrict__ part) {
   __shared__ double red[kStencilThreads / 64];
+  // a step that has already reached its end time launches nothing useful
+  if (it->done) return;
+  const double hde = it->hde;
+  // after a failed attempt the free space restarts from dh_e/dt
+  warm = warm && !it->cold;
   const long long n = (long long)G.nx * G.ny;
   const long long i0 = (long long)blockIdx.x * (kStencilThreads * kStencilNpt) + threadIdx.x;
   double acc = 0.0;
@@ -360,6 +366,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     shift = pp.in ? parts_sum(pp.in, pp.nin) * it->inv_nout : it->A;
     if (pp.in && blockIdx.x == 0 && threadIdx.x == 0) it->A = shift;
   }
+  // MODE 0 subtracts dh_e/dt of the iteration state
+  if constexpr (MODE == 0) hde = it->hde;
   double acc = 0.0, acc_film = 0.0;
   cx<T> v[RMAX];
 #pragma unroll
@@ -600,7 +608,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     MAG_WAVES_PER_EU(FilmRowShape<M, T>::WAVES_EU)
     film_rows_fused(T *__restrict__ X, const uint8_t *__restrict__ flags, cx<T> *__restrict__ S,
                     const T *__restrict__ w, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
-                    FilmGeom G, double hde, double lam, Parts pp, IterState *__restrict__ it, int keep,
+                    FilmGeom G, double lam, Parts pp, IterState *__restrict__ it, int keep,
                     double *__restrict__ res) {
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
@@ -627,6 +635,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   // do not depend on it and nothing is written before the test), so its load
   // does not delay theirs: -0.2 / -0.4 us on passes 2 / 4 at 2048^2
   if (it->done) return;
+  const double hde = it->hde;
   double cst;
   if constexpr (MODE == 6) {
     cst = parts_sum(pp.in, pp.nin) * it->inv_nout;   // C
@@ -1267,8 +1276,7 @@ static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid)
 }
 
 template <typename T, int MODE>
-static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int kid, int keep = 1,
-                      double *out = nullptr) {
+static int film_fused(mag_ctx *c, T *X, const T *w, Parts pp, int kid, int keep = 1, double *out = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfLaunch ps(c, kid);
@@ -1276,7 +1284,7 @@ static int film_fused(mag_ctx *c, T *X, const T *w, double hde, Parts pp, int ki
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     MAG_TIMED_LAUNCH(ps, (film_rows_fused<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, c->d_flags,
-                       f.S, w, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it, keep, out);
+                       f.S, w, f.twM, f.twN, G, c->lambda, pp, c->d_it, keep, out);
   });
   return MAG_OK;
 }
@@ -1333,12 +1341,54 @@ static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
     return rc;
   if ((rc = film_col<T>(c, 0))) return rc;
   const bool last_fixed = c->fixed_iters > 0 && i == c->fixed_iters - 1;
-  if ((rc = film_fused<T, 6>(c, f.G, f.w2, hde, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G,
+  if ((rc = film_fused<T, 6>(c, f.G, f.w2, parts(pr.C, pr.nb, pr.R, pr.A), K_FILM_ROWS_INV_G,
                              c->fixed_iters <= 0 ? 1 : 0, last_fixed ? out : nullptr)))
     return rc;
   if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, i)))) return rc;
   if (last_fixed) return MAG_OK;
-  return film_fused<T, 7>(c, f.H, f.w1f, hde, parts(pr.A, pr.nb, pr.C, pr.F), K_FILM_ROWS_INV_UPD);
+  return film_fused<T, 7>(c, f.H, f.w1f, parts(pr.A, pr.nb, pr.C, pr.F), K_FILM_ROWS_INV_UPD);
+}
+
+static FilmLaw film_law(const mag_ctx *c) {
+  FilmLaw law;
+  law.e0 = c->e0;
+  law.nm1 = c->nexp - 1.0;
+  law.rho_out = c->rho_out;
+  law.lmax = std::log(1e30) / (c->nexp - 1.0 > 1e-12 ? c->nexp - 1.0 : 1e-12);
+  law.jc0 = c->jc0;
+  law.has_jc = c->has_jc_map ? 1 : 0;
+  return law;
+}
+
+// The right-hand side with a fixed inner count, enqueued only: the iteration
+// state (dh_e/dt included) has been set on the device by the caller, the
+// free-space iterate holds the warm start, and the last evaluation writes
+// `out`.  No host synchronisation and no host-side decision, so the launches
+// can be captured in a graph.
+template <typename T>
+static int film_rhs_enqueue_t(mag_ctx *c, const double *state, double *out) {
+  FilmPtrs<T> f = fptrs<T>(c);
+  const FilmGeom G = fgeom(c);
+  const FilmLaw law = film_law(c);
+  const int nbs = film_stencil_blocks(c);
+  {
+    ProfLaunch ps(c, K_FILM_STENCIL);
+    MAG_TIMED_LAUNCH(ps, (film_stencil<T>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
+                     c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, 1,
+                     film_regions<T>(c).X);
+  }
+  for (int i = 0; i < c->fixed_iters; ++i) {
+    c->cur_iter = i;
+    if (int rc = film_iteration<T>(c, 0.0, i, nbs, out)) return rc;
+  }
+  c->cur_iter = -1;
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
+int film_rhs_enqueue(mag_ctx *c, const double *state, double *out) {
+  if (c->fixed_iters <= 0) return set_error(c, MAG_E_STATE, "an enqueued right-hand side needs a fixed count");
+  return c->prec == MAG_FP64 ? film_rhs_enqueue_t<double>(c, state, out) : film_rhs_enqueue_t<float>(c, state, out);
 }
 
 template <typename T>
@@ -1352,20 +1402,15 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   is.fixed = c->fixed_iters;
   is.thr = c->tol * (std::fabs(hde) > 1.0 ? std::fabs(hde) : 1.0);
   is.inv_nout = c->nout > 0 ? 1.0 / (double)c->nout : 0.0;
+  is.hde = hde;
   if (int rc0 = run_iter_init(c, is)) return rc0;
-  FilmLaw law;
-  law.e0 = c->e0;
-  law.nm1 = c->nexp - 1.0;
-  law.rho_out = c->rho_out;
-  law.lmax = std::log(1e30) / (c->nexp - 1.0 > 1e-12 ? c->nexp - 1.0 : 1e-12);
-  law.jc0 = c->jc0;
-  law.has_jc = c->has_jc_map ? 1 : 0;
+  const FilmLaw law = film_law(c);
   const long long n = c->nnode;
   const int nbs = film_stencil_blocks(c);
   {
     ProfLaunch ps(c, K_FILM_STENCIL);
     MAG_TIMED_LAUNCH(ps, (film_stencil<T>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat, c->d_flags,
-                       reinterpret_cast<const T *>(c->d_jc), f.H, G, law, hde, c->warm_valid ? 1 : 0,
+                       reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, c->warm_valid ? 1 : 0,
                        film_regions<T>(c).X);
   }
   int rc = MAG_OK;

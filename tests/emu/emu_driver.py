@@ -90,6 +90,41 @@ def run_rhs(L, h, state, t):
     return rc, it.value, out.numpy()
 
 
+def capture_check(L):
+    """mag_integrate_captured (step control on the device, attempts replayed
+    from a captured graph) against mag_integrate (host-driven) on the same
+    film with a fixed inner count: same accepted and rejected attempts and the
+    same final state, bit for bit (host and emulated device share one libm);
+    a second run from the same start reuses the graph and repeats the result."""
+    fails = 0
+    for prec, chunk in ((0, 3), (1, 4)):
+        case = film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2, n=19.0)
+        case["state"] = np.zeros_like(case["state"])
+        res = []
+        for mode in ("host", "captured", "captured"):
+            h, keep = setup(L, case, prec, fixed=2)
+            y = Dev(np.zeros_like(case["state"]))
+            if mode == "host":
+                ns = ctypes.c_int(0)
+                rc = L.mag_integrate(h, P(y), 0.0, 0.02, 1e-3, 1e-6, None, 0, ctypes.byref(ns))
+                res.append((rc, ns.value, None, y.numpy()))
+            else:
+                na, nr, tr = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+                rc = L.mag_integrate_captured(h, P(y), 0.0, 0.02, 1e-3, 1e-6, chunk, 100000, ctypes.byref(na),
+                                              ctypes.byref(nr), ctypes.byref(tr))
+                if rc != 0:
+                    print("   captured rc=%d %s" % (rc, L.mag_last_error(h)), flush=True)
+                res.append((rc, na.value, tr.value, y.numpy()))
+            L.mag_destroy(h)
+        (r0, n0, _, y0), (r1, n1, t1, y1), (r2, n2, t2, y2) = res
+        ok = r0 == r1 == r2 == 0 and n0 == n1 == n2 and t1 == t2 == 0.02 and np.array_equal(y0, y1) \
+            and np.array_equal(y1, y2)
+        fails += not ok
+        print("capture prec=%d chunk=%d host steps=%d captured steps=%d/%d t=%s max|dy|=%.3e %s" %
+              (prec, chunk, n0, n1, n2, t1, float(np.abs(y0 - y1).max()), "ok" if ok else "FAIL"), flush=True)
+    return fails
+
+
 def main(path, which):
     from oracle import bulk, film
     L = load(path)
@@ -113,6 +148,8 @@ def main(path, which):
                                                       shift=(1, -2, 3), n=25.0), prec, fixed),
                           ("bulk-16x64x32", bulk_case(16, 64, 32, L=(1.0, 4.0, 2.0), half=(0.45, 1.1, 0.7),
                                                       jc_s=0.2, n=50.0), prec, fixed)]
+    if which in ("capture", "all"):
+        fails += capture_check(L)
     if which in ("film", "all"):
         cases += [("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2),
                   ("film", film_case(16, 32, L=(1.0, 2.0), kind="ring", rho_out=20.0), 1, 1),

@@ -97,6 +97,19 @@ using std::sqrt;
 typedef int hipError_t;
 typedef void *hipStream_t;
 typedef void *hipEvent_t;
+// Stream capture: launches made while capturing are recorded and run when
+// the graph is launched; synchronisation and copies during a capture are
+// errors (they are not capturable on the device either).
+namespace emu {
+struct Graph {
+  std::vector<std::function<void()>> ops;
+};
+inline bool capturing = false;
+inline Graph *cap_graph = nullptr;
+}  // namespace emu
+typedef emu::Graph *hipGraph_t;
+typedef emu::Graph *hipGraphExec_t;
+enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipStreamCaptureModeThreadLocal = 1 };
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
 enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
 
@@ -274,6 +287,7 @@ namespace emu {
 // device (or pinned) allocation holding all n bytes, a host side must not be
 // device memory.
 inline hipError_t checked_copy(void *d, const void *s, size_t n, hipMemcpyKind kind, const char *call) {
+  if (capturing) fail("copy during stream capture (%p, %s)", d, call);
   if (n == 0) return hipSuccess;
   uintptr_t db = 0, sb = 0;
   size_t dl = 0, sl = 0;
@@ -342,7 +356,50 @@ inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) {
   if (k == emu::DEVICE) emu::poison_device(true);
   return hipSuccess;
 }
-inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) {
+  if (emu::capturing) emu::fail("hipStreamSynchronize during stream capture (%p, %s)", nullptr, "not capturable");
+  return hipSuccess;
+}
+inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
+  static int dummy[64];
+  static int k = 0;
+  *s = &dummy[(k++) & 63];
+  return hipSuccess;
+}
+inline hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) {
+  *e = nullptr;
+  return hipSuccess;
+}
+inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
+inline hipError_t hipStreamBeginCapture(hipStream_t, int) {
+  if (emu::capturing) emu::fail("nested stream capture (%p, %s)", nullptr, "hipStreamBeginCapture");
+  emu::capturing = true;
+  emu::cap_graph = new emu::Graph();
+  return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
+  emu::capturing = false;
+  *g = emu::cap_graph;
+  emu::cap_graph = nullptr;
+  return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, void *, void *, size_t) {
+  *x = new emu::Graph(*g);
+  return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g) {
+  delete g;
+  return hipSuccess;
+}
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t x) {
+  delete x;
+  return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t) {
+  for (auto &op : x->ops) op();
+  return hipSuccess;
+}
 inline hipError_t hipGetDevice(int *d) {
   *d = 0;
   return hipSuccess;
@@ -446,6 +503,7 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t shm, A... args) {
     int i = 0;
     std::apply([&](const auto &...x) { (emu::check_arg(x, kname, i++), ...); }, conv);
   }
+  auto run = [=]() mutable {
   emu::poison_device(false);
   emu::bDim = b;
   emu::gDim = g;
@@ -468,6 +526,9 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t shm, A... args) {
         std::free(d);
       }
   emu::poison_device(true);
+  };
+  if (emu::capturing) emu::cap_graph->ops.push_back(run);
+  else run();
 }
 #define hipLaunchKernelGGL(K, G, B, S, STREAM, ...) emu_launch(K, dim3(G), dim3(B), (size_t)(S), __VA_ARGS__)
 

@@ -30,7 +30,7 @@ def _libasan():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("which", ["film", "bulk", "bulk32"])
+@pytest.mark.parametrize("which", ["film", "capture", "bulk", "bulk32"])
 def test_emulated_kernels_in_bounds_and_match_oracle(which, tmp_path):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")

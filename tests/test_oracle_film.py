@@ -374,3 +374,22 @@ def test_relaxation_bound_of_the_staggered_iteration():
     p, g = _ring_512(0.7, sigma=None)
     rs = _residuals(p, g, 0.6, (1, 100))
     assert rs[1] < rs[0] and rs[1] > 1e3 * p.tol
+
+
+def test_non_finite_fixed_count_evaluation_fails_and_starts_the_next_cold():
+    """Sec. 2.2: a failed evaluation makes the integrator cut the step, and the
+    warm start comes from the previous (successful) call.  A fixed-count
+    right-hand side whose residual is not finite (FP64 power-law overflow)
+    reports a failure and clears the warm start: the next call equals a call
+    from a cold start, and an adaptive run across such attempts recovers."""
+    p = _prob(32, 32, n=19.0, fixed_iters=3)
+    g = W.film_snapshot(p.material, p.dx, delta=0.4, seed=3)
+    gd, it, st = film.rhs(p, g, 0.1)
+    assert st == 0 and p.warm is not None
+    bad = g * 1e30                               # |j|^18 overflows
+    gb, it, st = film.rhs(p, bad, 0.1)
+    assert st == film.NOT_FINITE and gb is None and p.warm is None
+    g1, _, st1 = film.rhs(p, g, 0.12)
+    p.reset_warm_start()
+    g2, _, st2 = film.rhs(p, g, 0.12)
+    assert st1 == st2 == 0 and np.array_equal(g1, g2)
