@@ -18,8 +18,9 @@ superconductivity", that it follows):
 * ``bs23``    -- explicit Bogacki-Shampine 3(2) pair with step control, the
                  integrator family of Matlab's ode23 named in Sec. 2.2.
 * ``adjoint`` -- hand-written vector-Jacobian products of the film
-                 right-hand side (transposes of the operators above), the
-                 frozen-step BS23 step and the h_z post-processing.
+                 right-hand side and of the fixed-count bulk right-hand side
+                 (transposes of the operators above), the frozen-step BS23
+                 step and the h_z post-processing.
 * ``bean``    -- Bean critical-state closed forms for the infinite strip and
                  the thin disk, the large-n limits used in Sec. 2.3.
 

@@ -1,5 +1,6 @@
 """Vector-Jacobian products of the right-hand side, oracle form.  TEST
-INFRASTRUCTURE ONLY.
+INFRASTRUCTURE ONLY.  Film (Sec. 2) below; bulk (Sec. 3) at the end of the
+module.
 
 The film right-hand side f(g, t) of Sec. 2.2 is the composition
 
@@ -225,3 +226,114 @@ def film_hz_vjp(prob, hz_bar):
     """Transpose of g -> h_z = h_e + F^{-1}[|k|/2 F(g)] (Sec. 2.1): the
     multiplier is real and even, so the operator is symmetric."""
     return film.apply_multiplier(hz_bar, prob.K2)
+
+
+# ------------------------------------------------------------------ bulk (Sec. 3)
+# The bulk right-hand side of Sec. 3.1 is the composition
+#
+#     h  --C (Ampere)-->  j  --power law (13)-->  e  --(-C^T), eq. (14)-->  dh_in
+#        --iteration (18) on the free space-->  dh.
+#
+# Iteration (18) updates only the free-space edges: with H^i = dh^i,
+#     H^{i+1}_out = dh_e + P_out Phi M_in C H^i,     H_in fixed,
+# (M_in: mask to inside faces, Phi the Biot-Savart operator of (16)-(17)),
+# so with A = P_out Phi M_in C and a fixed count k started from a constant
+# warm start W, the result is
+#     dh = E_in H_in + E_out H_out^k,   H_out^k = A_oo^k W + sum_{m<k} A_oo^m (A_oi H_in + dh_e),
+# and its transpose applied to a cotangent y_bar is
+#     H_in_bar = y_bar_in + A_oi^T s,   s = sum_{m<k} (A_oo^T)^m y_bar_out,
+#     A^T = C^T M_in Phi^T P_out.
+# Phi^T has the conjugate-transposed symbol of Phi.  H_in_bar is then pulled
+# back through (14), the power law and Ampere's law, and through the face jc
+# = mean of its two cells to the per-cell map.
+
+def bulk_phi_t(prob, w):
+    """Transpose of bulk.phi: the 3x3 symbol of Phi conjugated and transposed."""
+    W = [np.fft.fftn(w[c]) for c in range(3)]
+    dm, inv = prob.dminus, prob.inv_k2
+    cdm = [np.conj(d) for d in dm]
+    # Phi symbol rows: x <- (dy Fz - dz Fy), y <- (dz Fx - dx Fz), z <- (dx Fy - dy Fx); times inv.
+    # Transpose-conjugate: component b of the result collects conj(M[a][b]) W_a.
+    P = [(cdm[2] * W[1] - cdm[1] * W[2]) * inv,       # b = x: M[y][x] = dz, M[z][x] = -dy
+         (-cdm[2] * W[0] + cdm[0] * W[2]) * inv,      # b = y: M[x][y] = -dz, M[z][y] = dx
+         (cdm[1] * W[0] - cdm[0] * W[1]) * inv]       # b = z: M[x][z] = dy, M[y][z] = -dx
+    return np.stack([np.fft.ifftn(p).real for p in P])
+
+
+def _avg4_t(g, a, b):
+    """Transpose of bulk._avg4(., a, b)."""
+    return 0.25 * (shift(g, a, 1) + g + shift(shift(g, a, 1), b, -1) + shift(g, b, -1))
+
+
+def bulk_stencil_vjp(prob, h, hbar):
+    """Transpose of h -> dh_in = -C^T e(C h) applied to hbar (zero off the
+    inside edges).  Returns (h_bar, jc_cell_bar)."""
+    from . import bulk
+    AX = bulk.AXIS
+    j = bulk.curl(prob, h)
+    # e_a = rho(s_a) j_a, s_a^2 = j_a^2 + sum_{b != a} avg4(j_b, a, b)^2
+    avg = {}
+    s = []
+    for a in range(3):
+        acc = j[a] ** 2
+        for b in range(3):
+            if b != a:
+                avg[(a, b)] = bulk._avg4(j[b], AX[a], AX[b])
+                acc = acc + avg[(a, b)] ** 2
+        s.append(np.sqrt(acc))
+    nm1 = prob.n - 1.0
+    # cotangent of e: d(dh_in) = -C^T de  ->  e_bar = -C hbar
+    ebar = -bulk.curl(prob, hbar)
+    jbar = np.zeros_like(j)
+    jcf_bar = np.zeros_like(j)
+    for a in range(3):
+        jce = prob.jc_face[a]
+        sc = prob.sc_face[a]
+        sa = s[a]
+        pos = sa > 0
+        s2 = np.where(pos, sa * sa, 1.0)
+        rho_pl = (prob.e0 / jce) * (sa / jce) ** nm1
+        rho = np.where(sc, rho_pl, prob.rho_out)
+        # de_a/dj_a = rho (1 + (n-1) j_a^2 / s^2); de_a/d avg_b = rho (n-1) j_a avg_b / s^2 (power law only)
+        fac = np.where(sc & pos, rho_pl * nm1 / s2, 0.0)
+        jbar[a] += ebar[a] * (rho + fac * j[a] * j[a])
+        for b in range(3):
+            if b != a:
+                jbar[b] += _avg4_t(ebar[a] * fac * j[a] * avg[(a, b)], AX[a], AX[b])
+        # de_a/djc_face = -n e_a / jc (superconducting faces)
+        e_pl = rho_pl * j[a]
+        jcf_bar[a] = np.where(sc, ebar[a] * (-prob.n * e_pl / jce), 0.0)
+    hb = bulk.curl_t(prob, jbar)
+    # face jc = mean of the two cells: an a-face at (p,q,r) joins cells (p,q,r) and (p,q,r) - e_a
+    jc_bar = np.zeros(prob.shape)
+    for a in range(3):
+        jc_bar += 0.5 * (jcf_bar[a] + shift(jcf_bar[a], AX[a], 1))
+    return hb, jc_bar
+
+
+def bulk_iteration_vjp(prob, ybar, k):
+    """H_in_bar of the fixed-count iteration (18) (k updates) for the cotangent
+    ybar of dh (all edges).  Returns H_in_bar on inside edges (0 elsewhere)."""
+    from . import bulk
+    ie, oe = prob.in_edge, prob.out_edge
+    mu = np.where(oe, ybar, 0.0)
+    s = np.zeros_like(ybar)
+    nu = mu
+    for m in range(k):
+        s = s + nu
+        if m < k - 1:
+            nu = np.where(oe, bulk.curl_t(prob, prob.in_face * bulk_phi_t(prob, np.where(oe, nu, 0.0))), 0.0)
+    hin_bar = np.where(ie, ybar, 0.0) + np.where(ie, bulk.curl_t(prob, prob.in_face * bulk_phi_t(prob, np.where(oe, s, 0.0))), 0.0)
+    return hin_bar
+
+
+def bulk_rhs_vjp(prob, h, t, ybar, jc0=1.0):
+    """(h_bar, jc_map_bar) for the cotangent ybar of the fixed-count bulk
+    right-hand side (prob.fixed_iters updates of (18); the warm start and
+    dh_e are constants)."""
+    k = prob.fixed_iters
+    if k <= 0:
+        raise ValueError("the bulk VJP is the transpose of a fixed inner count")
+    hin_bar = bulk_iteration_vjp(prob, ybar, k)
+    hb, jcb = bulk_stencil_vjp(prob, h, hin_bar)
+    return hb, jc0 * jcb

@@ -1,11 +1,14 @@
 """Pins of the oracle's vector-Jacobian products (oracle/adjoint.py) against
 the oracle's forward right-hand side, which is pinned on its own: dot-product
 tests <w, J v> = <J^T w, v> with J v from central differences, and a dense
-Jacobian assembled column by column where the map is affine."""
+Jacobian assembled column by column where the map is affine.  Film (Sec. 2)
+and bulk (Sec. 3)."""
 import numpy as np
 import pytest
 
-from oracle import adjoint, film
+from oracle import adjoint, bulk, film
+from oracle.field import AppliedField
+from paper_1801_04869_amd import workloads as W
 from tests._cases import film_case, make_oracle
 
 
@@ -171,3 +174,79 @@ def test_film_trajectory_gradient_finite_differences():
     assert abs(dL - np.vdot(gb, v)) < 1e-6 * abs(dL)
     dL = (loss(g0, jc + eps * u) - loss(g0, jc - eps * u)) / (2 * eps)
     assert abs(dL - np.vdot(jb, u)) < 1e-6 * abs(dL)
+
+
+# ------------------------------------------------------------------ bulk (Sec. 3)
+def _bulk_prob(fixed=2, n=7.0, jc_s=0.2, rho_out=3.0, seed=4):
+    nx, ny, nz = 12, 10, 8
+    L = (1.5, 1.25, 1.0)
+    m = W.bulk_box(nx, ny, nz, *L, 0.75, 0.6, 0.5)
+    m = np.roll(m, (1, -1, 0), axis=(0, 1, 2))
+    # one normal-conducting cell block inside the sample (rho_out path)
+    m[3:5, 4:6, 5:7][m[3:5, 4:6, 5:7] == 1] = 2
+    jc = W.lognormal_jc((nz, ny, nx), jc_s, 2.0, seed) if jc_s > 0 else None
+    fld = AppliedField(kind=0, direction=(0.3, -0.2, 0.9), rate=0.7)
+    p = bulk.BulkProblem(nx, ny, nz, *L, m, jc_cell=jc, n=n, rho_out=rho_out, fixed_iters=fixed, field=fld)
+    he = fld.h(0.3)
+    h = W.bulk_snapshot(m, 2 * L[0] / nx, he, delta=0.3, seed=seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    h = h + 0.05 * rng.standard_normal(h.shape)
+    return p, h, jc
+
+
+def test_bulk_phi_transpose_dot_product():
+    """<Phi j, w> = <j, Phi^T w> for random face and edge fields (the Fourier
+    symbol of Phi conjugated and transposed)."""
+    p, h, _ = _bulk_prob()
+    rng = np.random.default_rng(11)
+    j = rng.standard_normal((3,) + p.shape)
+    w = rng.standard_normal((3,) + p.shape)
+    lhs = np.sum(bulk.phi(p, j) * w)
+    rhs = np.sum(j * adjoint.bulk_phi_t(p, w))
+    assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(j) * np.linalg.norm(w)
+
+
+def _bulk_f(p, h, t=0.3):
+    p.reset_warm_start()
+    v, it, st = bulk.rhs(p, h, t)
+    assert st == 0
+    return v
+
+
+@pytest.mark.parametrize("fixed", [1, 3])
+def test_bulk_rhs_vjp_central_differences(fixed):
+    """<f(h + eps v) - f(h - eps v), ybar> / (2 eps) = <v, f'(h)^T ybar> for the
+    fixed-count bulk right-hand side (power law with n = 7, a normal-conducting
+    block, log-normal jc), random directions v and cotangents ybar."""
+    p, h, _ = _bulk_prob(fixed=fixed)
+    rng = np.random.default_rng(21 + fixed)
+    ybar = rng.standard_normal(h.shape)
+    hb, jcb = adjoint.bulk_rhs_vjp(p, h, 0.3, ybar)
+    for trial in range(2):
+        v = rng.standard_normal(h.shape)
+        eps = 1e-6
+        fd = np.sum((_bulk_f(p, h + eps * v) - _bulk_f(p, h - eps * v)) * ybar) / (2 * eps)
+        an = np.sum(v * hb)
+        assert abs(fd - an) < 1e-6 * max(abs(an), np.linalg.norm(hb) * np.linalg.norm(v) * 1e-3)
+
+
+def test_bulk_rhs_vjp_jc_map_central_differences():
+    """The cotangent of the per-cell jc map against central differences of the
+    fixed-count right-hand side in random map directions."""
+    p, h, jc = _bulk_prob(fixed=2)
+    rng = np.random.default_rng(31)
+    ybar = rng.standard_normal(h.shape)
+    hb, jcb = adjoint.bulk_rhs_vjp(p, h, 0.3, ybar)
+    base = p.jc_cell.copy()
+    for trial in range(2):
+        d = rng.standard_normal(base.shape)
+        eps = 1e-6
+        vals = []
+        for sgn in (1, -1):
+            q, _, _ = _bulk_prob(fixed=2)
+            q.jc_cell = base * (1 + sgn * eps * d)
+            q._classify()
+            vals.append(_bulk_f(q, h))
+        fd = np.sum((vals[0] - vals[1]) * ybar) / (2 * eps)
+        an = np.sum(jcb * base * d)
+        assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12)
