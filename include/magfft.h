@@ -63,8 +63,14 @@ enum mag_status {
 
 enum mag_precision {
   MAG_FP64 = 0,  /* everything in double precision */
-  MAG_MIXED = 1  /* FFTs, Fourier multipliers and the power law in float; state,
+  MAG_MIXED = 1, /* FFTs, Fourier multipliers and the power law in float; state,
                     time stepping, step control and all iteration sums in double */
+  MAG_MIXED_FINAL64 = 2  /* films only: the iteration (11)-(12) as MAG_MIXED, then the
+                    returned dg/dt evaluated once more by (11) in double from the
+                    iterate the float iteration stopped at (FFTs, multiplier 2/|k|
+                    and the free-space mean in double).  Observables and the VJP
+                    are those of MAG_MIXED.  mag_create returns MAG_E_ARG for it
+                    with dim = 3. */
 };
 
 enum mag_field_kind {

@@ -12,7 +12,7 @@ from . import _lib
 
 OK, NOT_CONVERGED, STEP_UNDERFLOW = 0, 1, 2
 E_ARG, E_STATE, E_HIP, E_NOMEM, E_NUMERIC = -1, -2, -3, -4, -5
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_FINAL64 = 0, 1, 2
 RAMP, SINE, ROTATE = 0, 1, 2
 
 

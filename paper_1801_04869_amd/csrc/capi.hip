@@ -88,7 +88,7 @@ static hipEvent_t pool_get(mag_ctx *c) {
 static const char *kNames[K_COUNT] = {
     "film_stencil", "film_rows_fwd_h", "film_cols", "film_rows_inv_g", "film_rows_fwd_g", "film_rows_inv_upd",
     "bulk_curl_box", "bulk_efield_box", "bulk_hdot_in", "bulk_x_fwd", "bulk_y_fwd", "bulk_z_phi",
-    "bulk_y_inv", "bulk_x_inv", "finalize", "misc", "rk", "vjp"};
+    "bulk_y_inv", "bulk_x_inv", "finalize", "misc", "rk", "vjp", "film_final64"};
 
 void prof_begin(mag_ctx *c, int kid, ProfRec *r) {
   r->a = r->b = nullptr;
@@ -504,11 +504,13 @@ static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (
 
 static void free_all(mag_ctx *c) {
   void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
-                  c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_w};
+                  c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_w,
+                  c->d_tw64, c->d_it64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_mat = c->d_flags = nullptr;
-  c->d_jc = c->d_H = c->d_G = c->d_S = c->d_box = c->d_tw = c->d_w = nullptr;
+  c->d_jc = c->d_H = c->d_G = c->d_S = c->d_box = c->d_tw = c->d_w = c->d_tw64 = nullptr;
+  c->d_it64 = nullptr;
   c->d_jc64 = c->d_part = c->d_sym = c->d_rk = c->d_red = nullptr;
   c->d_it = nullptr;
   c->nred = 0;
@@ -518,7 +520,8 @@ int mag_create(mag_ctx **out, int dim, int precision, void *hip_stream) {
   if (!out) return MAG_E_ARG;
   *out = nullptr;
   if (dim != 2 && dim != 3) return MAG_E_ARG;
-  if (precision != MAG_FP64 && precision != MAG_MIXED) return MAG_E_ARG;
+  if (precision != MAG_FP64 && precision != MAG_MIXED && precision != MAG_MIXED_FINAL64) return MAG_E_ARG;
+  if (precision == MAG_MIXED_FINAL64 && dim != 2) return MAG_E_ARG;
   mag_ctx *c = new (std::nothrow) mag_ctx();
   if (!c) return MAG_E_NOMEM;
   c->dim = dim;
@@ -632,6 +635,7 @@ int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, doubl
   MAG_HIP(c, hipMalloc(&c->d_tw, ntw * 2 * ts));
   MAG_HIP(c, hipMalloc(&tmp, tw.size() * sizeof(double)));
   MAG_HIP(c, hipMemcpy(tmp, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (c->prec == MAG_MIXED_FINAL64) MAG_HIP(c, hipMalloc(&c->d_tw64, ntw * 2 * sizeof(double)));
   {
   ProfScope ps(c, K_MISC);
   if (c->prec == MAG_FP64)
@@ -640,6 +644,9 @@ int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, doubl
   else
     hipLaunchKernelGGL((fill_twiddles<float>), dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, c->stream,
                        reinterpret_cast<cx<float> *>(c->d_tw), tmp, ntw);
+  if (c->d_tw64)
+    hipLaunchKernelGGL((fill_twiddles<double>), dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<cx<double> *>(c->d_tw64), tmp, ntw);
   }
   MAG_HIP(c, hipGetLastError());
   MAG_HIP(c, hipStreamSynchronize(c->stream));

@@ -73,6 +73,7 @@ enum KernelId {
   K_MISC,
   K_RK,
   K_VJP,
+  K_FILM_FINAL64,
   K_COUNT
 };
 
@@ -132,6 +133,8 @@ struct mag_ctx {
   mag::IterState *d_it = nullptr;
   mag::IterState *h_it = nullptr; // pinned
   void *d_tw = nullptr;           // twiddle tables (precision type)
+  void *d_tw64 = nullptr;         // MAG_MIXED_FINAL64: the same tables in double
+  mag::IterState *d_it64 = nullptr;   // MAG_MIXED_FINAL64: gate of the final evaluation
   long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
   double *d_sym = nullptr;        // per-axis symbol tables (double)
   long long sym_off[8] = {0};

@@ -822,6 +822,9 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           X[ro + p] = val[e];
           if (out) acc += (double)val[e];
           acc2 += fabs((double)val[e]);
+        } else if constexpr (MODE == 6) {
+          xd[ro + p] = (double)val[e];
+          if (out) acc += (double)val[e];
         } else {
           xd[ro + p] = hde + (double)val[e];
         }
@@ -950,6 +953,40 @@ __global__ void __launch_bounds__(256) film_out(const T *__restrict__ Gm, double
                                                 const IterState *__restrict__ it) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i < n) out[i] = (double)Gm[i] - it->C;
+}
+
+// Final evaluation of a MAG_MIXED_FINAL64 right-hand side.  Its kernels run
+// once the float iteration has stopped after at least one evaluation (a
+// stop, the fixed count reached, or a non-finite residual); the launches of
+// an unfinished block of iterations, or of a step that has reached its end
+// time, return at once.  gate->done is their skip flag.
+__global__ void __launch_bounds__(64) final64_gate_k(const IterState *__restrict__ it, IterState *__restrict__ gate) {
+  if (threadIdx.x == 0) gate->done = (it->done && it->iters > 0) ? 0 : 1;
+}
+
+// x = H - dh_e/dt in double from the float iterate, all nodes.
+__global__ void __launch_bounds__(256) final64_lift_k(const float *__restrict__ H, double *__restrict__ x,
+                                                      long long n, const IterState *__restrict__ it,
+                                                      const IterState *__restrict__ gate) {
+  if (gate->done) return;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = (double)H[i] - it->hde;
+}
+
+// x <- x - C on all nodes, C = (sum of the per-block free-space sums) / #out,
+// summed in a fixed order by every wavefront.  Eight nodes per thread.
+constexpr int kFinal64Npt = 8;
+__global__ void __launch_bounds__(256) final64_sub_mean_k(double *__restrict__ x, long long n,
+                                                          const double *__restrict__ part, int np, double inv_nout,
+                                                          const IterState *__restrict__ gate) {
+  if (gate->done) return;
+  const double C = parts_sum(part, np) * inv_nout;
+  const long long i0 = (long long)blockIdx.x * (256 * kFinal64Npt) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kFinal64Npt; ++k) {
+    const long long i = i0 + (long long)k * 256;
+    if (i < n) x[i] -= C;
+  }
 }
 
 __global__ void __launch_bounds__(256) film_current(const double *__restrict__ g, double *__restrict__ j, int nx,
@@ -1187,19 +1224,23 @@ struct FilmPtrs {
   T *w1f;       // K1 1_out with NaN on film nodes
 };
 
+// The double pointers of a MAG_MIXED_FINAL64 context are those of its final
+// evaluation: the spectrum buffer (allocated for double) and the double
+// twiddles; it has no double iterate or weights.
 template <typename T>
 static FilmPtrs<T> fptrs(mag_ctx *c) {
   FilmPtrs<T> f;
-  f.H = reinterpret_cast<T *>(c->d_H);
-  f.G = reinterpret_cast<T *>(c->d_G);
+  const bool final64 = sizeof(T) == 8 && c->prec != MAG_FP64;
+  f.H = final64 ? nullptr : reinterpret_cast<T *>(c->d_H);
+  f.G = final64 ? nullptr : reinterpret_cast<T *>(c->d_G);
   f.S = reinterpret_cast<cx<T> *>(c->d_S);
-  const cx<T> *tw = reinterpret_cast<const cx<T> *>(c->d_tw);
+  const cx<T> *tw = reinterpret_cast<const cx<T> *>(final64 ? c->d_tw64 : c->d_tw);
   f.twM = tw + c->tw_off[0];
   f.twY = tw + c->tw_off[1];
   f.twN = tw + c->tw_off[3];
   f.k2x = c->d_sym + c->sym_off[0];
   f.k2y = c->d_sym + c->sym_off[1];
-  f.w1 = reinterpret_cast<T *>(c->d_w);
+  f.w1 = final64 ? nullptr : reinterpret_cast<T *>(c->d_w);
   f.w2 = f.w1 ? f.w1 + c->nnode : nullptr;
   f.w1f = f.w1 ? f.w1 + 2 * c->nnode : nullptr;
   return f;
@@ -1247,7 +1288,7 @@ static Parts parts(const double *in, int nin, double *out, double *out2 = nullpt
 }
 
 template <typename T, int MODE>
-static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, int kid) {
+static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, int kid, IterState *its = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfLaunch ps(c, kid);
@@ -1255,14 +1296,14 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, in
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     MAG_TIMED_LAUNCH(ps, (film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
-                       c->d_flags, f.S, f.twM, f.twN, G, hde, pp, c->d_it,
+                       c->d_flags, f.S, f.twM, f.twN, G, hde, pp, its ? its : c->d_it,
                        ((MODE == 0 || MODE == 5) && pp.out) ? (const T *)f.w1 : (const T *)nullptr);
   });
   return MAG_OK;
 }
 
 template <typename T, int MODE>
-static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid) {
+static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid, IterState *its = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfLaunch ps(c, kid);
@@ -1270,7 +1311,7 @@ static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid)
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     MAG_TIMED_LAUNCH(ps, (film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
-                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, pp, c->d_it);
+                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, pp, its ? its : c->d_it);
   });
   return MAG_OK;
 }
@@ -1306,15 +1347,16 @@ static int film_adj(mag_ctx *c, T *X, const T *w, AdjParts pp) {
 // which = 0: 2/|k|; which = 1: |k|/2.  pp.in != NULL: take the stop decision
 // of evaluation pp.iter from the residual sums pp.in first.
 template <typename T>
-static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)) {
+static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr), IterState *its = nullptr,
+                    int kid = K_FILM_COLS) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
-  ProfLaunch ps(c, K_FILM_COLS);
+  ProfLaunch ps(c, kid);
   FILM_SWITCH_N(G.ny, {
     using CS = FilmColShape<NN, T>;
     const int nblk = (G.kx - 1 + CS::P - 1) / CS::P;   // the kx = 0 and kx = M columns share a pencil
     MAG_TIMED_LAUNCH(ps, (film_cols<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x, f.k2y,
-                       1.0 / (double)c->nnode, which, f.twY, pp, c->d_it, c->h_it);
+                       1.0 / (double)c->nnode, which, f.twY, pp, its ? its : c->d_it, c->h_it);
   });
   return MAG_OK;
 }
@@ -1347,6 +1389,39 @@ static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
   if ((rc = film_col<T>(c, 1, parts(pr.R, pr.nb, nullptr, nullptr, i)))) return rc;
   if (last_fixed) return MAG_OK;
   return film_fused<T, 7>(c, f.H, f.w1f, parts(pr.A, pr.nb, pr.C, pr.F), K_FILM_ROWS_INV_UPD);
+}
+
+// The returned dg/dt of a MAG_MIXED_FINAL64 right-hand side: (11) once more
+// in double from the float iterate H the iteration stopped at,
+// gdot = K1 (H - dh_e) - C with C the free-space mean (Sec. 2.2), written to
+// out (which also holds H - dh_e in between).  The double spectrum reuses the
+// spectrum buffer, free once the iteration has stopped.  Enqueued only.
+static int film_final64(mag_ctx *c, double *out) {
+  const long long n = c->nnode;
+  const PartRegions pr = film_regions<float>(c);
+  double *part = pr.F + pr.nb;   // after the regions of the float iteration
+  const int nb64 = film_row_blocks<double>(c);
+  if (part + nb64 > c->d_part + c->npart) return set_error(c, MAG_E_STATE, "partial-sum buffer too small");
+  {
+    ProfScope ps(c, K_FILM_FINAL64);
+    hipLaunchKernelGGL(final64_gate_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->d_it64);
+    hipLaunchKernelGGL(final64_lift_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<const float *>(c->d_H), out, n, c->d_it, c->d_it64);
+  }
+  int rc;
+  if ((rc = film_fwd<double, 2>(c, nullptr, out, 0.0, parts(nullptr, 0, nullptr), K_FILM_FINAL64, c->d_it64)))
+    return rc;
+  if ((rc = film_col<double>(c, 0, parts(nullptr, 0, nullptr), c->d_it64, K_FILM_FINAL64))) return rc;
+  if ((rc = film_inv<double, 6>(c, nullptr, out, 0.0, parts(nullptr, 0, part), K_FILM_FINAL64, c->d_it64)))
+    return rc;
+  {
+    ProfScope ps(c, K_FILM_FINAL64);
+    const long long per = 256LL * kFinal64Npt;
+    hipLaunchKernelGGL(final64_sub_mean_k, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, c->stream, out, n,
+                       (const double *)part, nb64, c->nout > 0 ? 1.0 / (double)c->nout : 0.0, c->d_it64);
+  }
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
 }
 
 static FilmLaw film_law(const mag_ctx *c) {
@@ -1382,6 +1457,8 @@ static int film_rhs_enqueue_t(mag_ctx *c, const double *state, double *out) {
     if (int rc = film_iteration<T>(c, 0.0, i, nbs, out)) return rc;
   }
   c->cur_iter = -1;
+  if (c->prec == MAG_MIXED_FINAL64)
+    if (int rc = film_final64(c, out)) return rc;
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
@@ -1429,8 +1506,11 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
     issued += k;
     // out = G - C, enqueued before the poll: right whenever this block ends
     // the iteration (it is enqueued again after a further block otherwise);
-    // at a fixed count the last evaluation has written it already
-    if (c->fixed_iters <= 0) {
+    // at a fixed count the last evaluation has written it already.  The
+    // final double evaluation runs only if the block ends the iteration.
+    if (c->prec == MAG_MIXED_FINAL64) {
+      if ((rc = film_final64(c, out))) return rc;
+    } else if (c->fixed_iters <= 0) {
       ProfScope ps(c, K_MISC);
       hipLaunchKernelGGL((film_out<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, f.G, out, n,
                          c->d_it);
@@ -1637,14 +1717,21 @@ int film_alloc(mag_ctx *c) {
   const long long n = c->nnode;
   MAG_HIP(c, hipMalloc(&c->d_H, n * ts));
   MAG_HIP(c, hipMalloc(&c->d_G, n * ts));
-  MAG_HIP(c, hipMalloc(&c->d_S, c->nspec * 2 * ts));
+  // a MAG_MIXED_FINAL64 context runs its final evaluation in this buffer
+  MAG_HIP(c, hipMalloc(&c->d_S, c->nspec * 2 * (c->prec == MAG_MIXED_FINAL64 ? sizeof(double) : ts)));
   MAG_HIP(c, hipMalloc(&c->d_flags, n));
   MAG_HIP(c, hipMalloc(&c->d_mat, n));
-  c->npart = (int)((n + 255) / 256 + 2 * c->n[1] + 16);   // 256-node blocks, or up to 5 regions of row blocks
+  // 256-node blocks, or the regions of row blocks and stencil blocks of an
+  // iteration and the final double evaluation's row blocks
+  c->npart = (int)((n + 255) / 256 + 3 * c->n[1] + 16);
   MAG_HIP(c, hipMalloc(&c->d_part, (size_t)c->npart * sizeof(double)));
   MAG_HIP(c, hipMalloc(&c->d_w, 3 * n * ts));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
   MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
+  if (c->prec == MAG_MIXED_FINAL64) {
+    MAG_HIP(c, hipMalloc(&c->d_it64, sizeof(IterState)));
+    MAG_HIP(c, hipMemsetAsync(c->d_it64, 0, sizeof(IterState), c->stream));
+  }
   // |k|^2 per axis: k = 2 pi fftfreq(n, d)
   const int nx = c->n[0], ny = c->n[1];
   std::vector<double> sym;

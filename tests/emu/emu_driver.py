@@ -97,7 +97,7 @@ def capture_check(L):
     same final state, bit for bit (host and emulated device share one libm);
     a second run from the same start reuses the graph and repeats the result."""
     fails = 0
-    for prec, chunk in ((0, 3), (1, 4)):
+    for prec, chunk in ((0, 3), (1, 4), (2, 3)):
         case = film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2, n=19.0)
         case["state"] = np.zeros_like(case["state"])
         res = []
@@ -154,7 +154,10 @@ def main(path, which):
         cases += [("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2),
                   ("film", film_case(16, 32, L=(1.0, 2.0), kind="ring", rho_out=20.0), 1, 1),
                   ("film", film_case(128, 64, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2),
-                  ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 1, 3)]
+                  ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 1, 3),
+                  # mixed iteration with the final evaluation in double
+                  ("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 2, 2),
+                  ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 2, 3)]
     for name, case, prec, fixed in cases:
         h, keep = setup(L, case, prec, fixed=fixed)
         rc, it, out = run_rhs(L, h, case["state"], 0.2)

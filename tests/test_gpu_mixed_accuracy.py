@@ -58,16 +58,16 @@ def _grid(c, g0, t0, n_steps=None, t_end=None):
     return grid, y
 
 
-def _errors(mat, jc, g0, t0, fixed, tol, **run):
+def _errors(mat, jc, g0, t0, fixed, tol, prec=api.MIXED, **run):
     c64 = _ctx(api.FP64, mat, jc, fixed, tol)
     grid, y = _grid(c64, g0, t0, **run)
     r64 = _replay(c64, g0, grid)
-    r32 = _replay(_ctx(api.MIXED, mat, jc, fixed, tol), g0, grid)
+    r32 = _replay(_ctx(prec, mat, jc, fixed, tol), g0, grid)
     # the replay repeats the adaptive FP64 run
     assert np.array_equal(r64[0], y.cpu().numpy())
     e = {k: np.linalg.norm(a - b) / np.linalg.norm(b) for k, a, b in zip(("g", "hz", "j", "m"), r32, r64)}
-    print("fixed %d, tol %g: %d steps, t = %.6g .. %.6g; rel-L2 mixed vs FP64: %s" %
-          (fixed, tol, len(grid), t0, grid[-1][0] + grid[-1][1],
+    print("precision %d, fixed %d, tol %g: %d steps, t = %.6g .. %.6g; rel-L2 vs FP64: %s" %
+          (prec, fixed, tol, len(grid), t0, grid[-1][0] + grid[-1][1],
            ", ".join("%s %.2e" % kv for kv in e.items())), flush=True)
     return e
 
@@ -77,26 +77,38 @@ def _ring():
     return mat, W.lognormal_jc((N, N), 0.2, 8.0, 1801)
 
 
-def test_mixed_form_error_per_result_fixed_count():
+@pytest.mark.parametrize("prec", [api.MIXED, api.MIXED_FINAL64])
+def test_mixed_form_error_per_result_fixed_count(prec):
     """The benchmark's setting (Bean-like snapshot, 4 inner iterations): the
     two forms do the same arithmetic in different precisions, and every
     result stays within the mixed form's tolerance."""
     mat, jc = _ring()
     g0 = W.film_snapshot(mat, 2 * L / N, delta=0.15, seed=1801)
-    e = _errors(mat, jc, g0, 0.6, 4, 2e-4, n_steps=6)
+    e = _errors(mat, jc, g0, 0.6, 4, 2e-4, prec=prec, n_steps=6)
+    for k, v in e.items():
+        assert v < 1e-4, k
+
+
+def test_mixed_final64_form_error_per_result_converged():
+    """The trajectory of the converged test below with the returned dg/dt of
+    every right-hand side evaluated by (11) in double from the float iterate
+    (MAG_MIXED_FINAL64): every result within the mixed form's tolerance."""
+    mat, jc = _ring()
+    e = _errors(mat, jc, np.zeros((N, N)), 0.0, 0, 2e-4, prec=api.MIXED_FINAL64, t_end=0.005)
     for k, v in e.items():
         assert v < 1e-4, k
 
 
 def test_mixed_form_error_per_result_converged():
     """A trajectory from the virgin state (258 steps to t = 0.005) with the
-    converged inner iteration.  The per-right-hand-side difference at the end
-    state stays within the mixed form's tolerance; the per-result differences
-    carry that rounding along the trajectory (measured: g 3e-5, h_z 9e-4,
-    j 1.3e-3, m 2e-7; a ten times tighter stop tolerance leaves them
-    unchanged, so they do not come from the iteration's stopping point).  The
-    bound is five times the largest measured difference, far below what a
-    wrong term in the mixed path gives (order one)."""
+    converged inner iteration, MAG_MIXED.  The per-right-hand-side difference
+    at the end state stays within the mixed form's tolerance.  The
+    per-result differences carry the rounding of the FP32 evaluation of (11)
+    that produces each returned dg/dt along the trajectory (measured: g 3e-5,
+    h_z 9e-4, j 1.3e-3, m 2e-7; with that evaluation in double, the test
+    above, they fall below 5e-6).  The bound is five times the largest
+    measured difference, far below what a wrong term in the mixed path gives
+    (order one)."""
     mat, jc = _ring()
     g0 = np.zeros((N, N))
     e = _errors(mat, jc, g0, 0.0, 0, 2e-4, t_end=0.005)

@@ -19,7 +19,8 @@ if not torch.cuda.is_available():
 from oracle import bulk, film  # noqa: E402
 from paper_1801_04869_amd import api  # noqa: E402
 
-TOL = {api.FP64: 1e-10, api.MIXED: 1e-4}
+TOL = {api.FP64: 1e-10, api.MIXED: 1e-4, api.MIXED_FINAL64: 1e-4}
+FILM_PRECS = [api.FP64, api.MIXED, api.MIXED_FINAL64]
 
 # The first GPU run of the bulk tests faulted the GPU before any result came
 # back; the cause has not been shown on the CPU (the CPU emulation of the same
@@ -120,7 +121,7 @@ FILM_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("prec", FILM_PRECS)
 @pytest.mark.parametrize("ci", range(len(FILM_CASES)))
 @pytest.mark.parametrize("fixed", [1, 4])
 def test_film_rhs_fixed_iterations(prec, ci, fixed):
@@ -141,7 +142,7 @@ EDGE_SHAPES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("prec", FILM_PRECS)
 @pytest.mark.parametrize("ci", range(len(EDGE_SHAPES)))
 def test_film_rhs_extreme_shapes(prec, ci):
     """The smallest grid and the most elongated ones: row passes with fewer
@@ -158,7 +159,7 @@ def test_film_rhs_extreme_shapes(prec, ci):
     assert rel_l2(out, ref) < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("prec", FILM_PRECS)
 def test_film_rhs_converged_sequence(prec):
     case = film_case(128, 128, kind="rect", jc_s=0.2)
     ctx = make_gpu(case, prec)
@@ -434,7 +435,7 @@ def test_sample_touching_periodic_boundary():
 
 
 # ------------------------------------------------------------------ full-size workload
-@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("prec", FILM_PRECS)
 @pytest.mark.parametrize("mask", ["ring", "slot"])
 def test_film_2048_workload_matches_oracle(mask, prec):
     """The benchmarked workload (1024^2-cell ring / slotted square in a 2048^2
@@ -442,7 +443,8 @@ def test_film_2048_workload_matches_oracle(mask, prec):
     in the launch configuration the benchmark times: whole-field comparison."""
     import bench
     wl, mat, jc, g = bench.film_inputs(mask, 0.6)
-    ctx = bench.make_ctx("mixed" if prec == api.MIXED else "fp64", wl, mat, jc, fixed=4)
+    ctx = bench.make_ctx({api.FP64: "fp64", api.MIXED: "mixed", api.MIXED_FINAL64: "final64"}[prec], wl, mat, jc,
+                         fixed=4)
     st, it, out = _gpu_rhs(ctx, g, 0.6)
     from oracle.field import AppliedField
     f = wl["field"]
@@ -517,7 +519,7 @@ def _captured_and_host(case, prec, fixed, t1, chunk, state0=None):
     return ctx, (nh, obs, yh.cpu().numpy()), (na, nr, tr, yc.cpu().numpy())
 
 
-@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("prec", FILM_PRECS)
 def test_film_captured_integration_matches_host_driven(prec):
     """mag_integrate_captured (t and dt on the device, step attempts replayed
     from one captured graph of `chunk` attempts) against mag_integrate (step
