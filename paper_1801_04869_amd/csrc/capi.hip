@@ -505,12 +505,13 @@ static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (
 static void free_all(mag_ctx *c) {
   void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
                   c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_w,
-                  c->d_tw64, c->d_it64};
+                  c->d_tw64, c->d_it64, c->d_w64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_mat = c->d_flags = nullptr;
   c->d_jc = c->d_H = c->d_G = c->d_S = c->d_box = c->d_tw = c->d_w = c->d_tw64 = nullptr;
   c->d_it64 = nullptr;
+  c->d_w64 = nullptr;
   c->d_jc64 = c->d_part = c->d_sym = c->d_rk = c->d_red = nullptr;
   c->d_it = nullptr;
   c->nred = 0;

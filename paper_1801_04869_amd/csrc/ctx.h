@@ -135,6 +135,7 @@ struct mag_ctx {
   void *d_tw = nullptr;           // twiddle tables (precision type)
   void *d_tw64 = nullptr;         // MAG_MIXED_FINAL64: the same tables in double
   mag::IterState *d_it64 = nullptr;   // MAG_MIXED_FINAL64: gate of the final evaluation
+  double *d_w64 = nullptr;        // MAG_MIXED_FINAL64: w1 = K1 1_out in double
   long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
   double *d_sym = nullptr;        // per-axis symbol tables (double)
   long long sym_off[8] = {0};

@@ -311,11 +311,14 @@ __device__ __forceinline__ void row_tw_put(const RowTw<T, M, THREADS> &rt, const
 // MODE 2: rows of a double array.
 // MODE 5: rows of a double array minus A on free space (A summed from the
 //         per-block sums pp.in when given, else it->A).
+// MODE 3: rows of the float iterate xf minus dh_e (it->hde), per-block sums
+//         of w1 (xf - dh_e) over all nodes (the final double evaluation).
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
                   cx<T> *__restrict__ S, const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN,
-                  FilmGeom G, double hde, Parts pp, IterState *__restrict__ it, const T *__restrict__ w1) {
+                  FilmGeom G, double hde, Parts pp, IterState *__restrict__ it, const T *__restrict__ w1,
+                  const float *__restrict__ xf) {
   using RS = FilmRowShape<M, T>;
   using PL = typename RS::PL;
   constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
@@ -331,9 +334,20 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   const long long ro = (long long)(active ? q : 0) * G.nx;
   // MODE 0: this thread's nodes 2m, 2m+1 (m = j + rho TT) of H, their flags
   // and w1, all loaded before any is used (a row past ny reads row 0 and is
-  // not used).
+  // not used).  MODE 3: the same nodes of xf and w1.
   T h0[RMAX][2], w0[RMAX][2];
   uint16_t f0[RMAX];
+  if constexpr (MODE == 3) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const long long o = ro + 2 * (j + rho * TT);
+      const float2 hv = *reinterpret_cast<const float2 *>(xf + o);
+      h0[rho][0] = (T)hv.x;
+      h0[rho][1] = (T)hv.y;
+      w0[rho][0] = w1[o];
+      w0[rho][1] = w1[o + 1];
+    }
+  }
   if constexpr (MODE == 0) {
     const T *wsrc = w1 ? w1 : X;   // without w1 the values read are not used
 #pragma unroll
@@ -366,8 +380,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     shift = pp.in ? parts_sum(pp.in, pp.nin) * it->inv_nout : it->A;
     if (pp.in && blockIdx.x == 0 && threadIdx.x == 0) it->A = shift;
   }
-  // MODE 0 subtracts dh_e/dt of the iteration state
-  if constexpr (MODE == 0) hde = it->hde;
+  // MODE 0 and 3 subtract dh_e/dt of the iteration state
+  if constexpr (MODE == 0 || MODE == 3) hde = it->hde;
   double acc = 0.0, acc_film = 0.0;
   cx<T> v[RMAX];
 #pragma unroll
@@ -390,6 +404,10 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           acc += t;
           if (film) acc_film += t;
         }
+      } else if constexpr (MODE == 3) {
+        const double x = (double)h0[rho][e] - hde;
+        val[e] = (T)x;
+        acc += (double)w0[rho][e] * x;
       } else if constexpr (MODE == 1) {
         const double gd = (double)X[ro + p] - shift;
         if (!(flags[ro + p] & 1)) {
@@ -446,7 +464,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       if (threadIdx.x == 0) pp.out2[blk] = sf;
     }
   }
-  if constexpr (MODE == 0 || MODE == 5) {
+  if constexpr (MODE == 0 || MODE == 3 || MODE == 5) {
     if (pp.out) {
       const double sblk = block_total<RS::THREADS>(acc, red);
       if (threadIdx.x == 0) pp.out[blk] = sblk;
@@ -746,6 +764,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // MODE 4: X <- X - C - lambda value; sums of the new X over free space.
 // MODE 5: write the value; sums over free space, and sums of |value| over D
 //         (second half of part).
+// Final double evaluation:
+// MODE 6: write value - C (double), C = (sum of pp.in) / #out.
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -763,7 +783,11 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   const int q = q0 + pr;
   const bool active = q < G.ny;
   const long long ro = (long long)(active ? q : 0) * G.nx;
-  const double cmean = MODE == 4 ? it->C : 0.0;
+  // MODE 4: the free-space mean of the iteration state; MODE 6: from the
+  // per-block sums pp.in of the forward pass (MODE 3)
+  double cmean = 0.0;
+  if constexpr (MODE == 4) cmean = it->C;
+  if constexpr (MODE == 6) cmean = parts_sum(pp.in, pp.nin) * it->inv_nout;
   double acc2 = 0.0;
   cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
   {
@@ -823,15 +847,14 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           if (out) acc += (double)val[e];
           acc2 += fabs((double)val[e]);
         } else if constexpr (MODE == 6) {
-          xd[ro + p] = (double)val[e];
-          if (out) acc += (double)val[e];
+          xd[ro + p] = (double)val[e] - cmean;
         } else {
           xd[ro + p] = hde + (double)val[e];
         }
       }
     }
   }
-  if constexpr (MODE != 2) {
+  if constexpr (MODE != 2 && MODE != 6) {
     const double sblk = block_total<RS::THREADS>(acc, red);
     if (threadIdx.x == 0) pp.out[blk] = sblk;
   }
@@ -959,33 +982,13 @@ __global__ void __launch_bounds__(256) film_out(const T *__restrict__ Gm, double
 // once the float iteration has stopped after at least one evaluation (a
 // stop, the fixed count reached, or a non-finite residual); the launches of
 // an unfinished block of iterations, or of a step that has reached its end
-// time, return at once.  gate->done is their skip flag.
+// time, return at once.  gate->done is their skip flag; dh_e/dt and 1/#out
+// are copied from the iteration state.
 __global__ void __launch_bounds__(64) final64_gate_k(const IterState *__restrict__ it, IterState *__restrict__ gate) {
-  if (threadIdx.x == 0) gate->done = (it->done && it->iters > 0) ? 0 : 1;
-}
-
-// x = H - dh_e/dt in double from the float iterate, all nodes.
-__global__ void __launch_bounds__(256) final64_lift_k(const float *__restrict__ H, double *__restrict__ x,
-                                                      long long n, const IterState *__restrict__ it,
-                                                      const IterState *__restrict__ gate) {
-  if (gate->done) return;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) x[i] = (double)H[i] - it->hde;
-}
-
-// x <- x - C on all nodes, C = (sum of the per-block free-space sums) / #out,
-// summed in a fixed order by every wavefront.  Eight nodes per thread.
-constexpr int kFinal64Npt = 8;
-__global__ void __launch_bounds__(256) final64_sub_mean_k(double *__restrict__ x, long long n,
-                                                          const double *__restrict__ part, int np, double inv_nout,
-                                                          const IterState *__restrict__ gate) {
-  if (gate->done) return;
-  const double C = parts_sum(part, np) * inv_nout;
-  const long long i0 = (long long)blockIdx.x * (256 * kFinal64Npt) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kFinal64Npt; ++k) {
-    const long long i = i0 + (long long)k * 256;
-    if (i < n) x[i] -= C;
+  if (threadIdx.x == 0) {
+    gate->done = (it->done && it->iters > 0) ? 0 : 1;
+    gate->hde = it->hde;
+    gate->inv_nout = it->inv_nout;
   }
 }
 
@@ -1225,8 +1228,8 @@ struct FilmPtrs {
 };
 
 // The double pointers of a MAG_MIXED_FINAL64 context are those of its final
-// evaluation: the spectrum buffer (allocated for double) and the double
-// twiddles; it has no double iterate or weights.
+// evaluation: the spectrum buffer (allocated for double), the double
+// twiddles and w1 in double; it has no double iterate, G, w2 or w1f.
 template <typename T>
 static FilmPtrs<T> fptrs(mag_ctx *c) {
   FilmPtrs<T> f;
@@ -1240,9 +1243,9 @@ static FilmPtrs<T> fptrs(mag_ctx *c) {
   f.twN = tw + c->tw_off[3];
   f.k2x = c->d_sym + c->sym_off[0];
   f.k2y = c->d_sym + c->sym_off[1];
-  f.w1 = final64 ? nullptr : reinterpret_cast<T *>(c->d_w);
-  f.w2 = f.w1 ? f.w1 + c->nnode : nullptr;
-  f.w1f = f.w1 ? f.w1 + 2 * c->nnode : nullptr;
+  f.w1 = reinterpret_cast<T *>(final64 ? c->d_w64 : c->d_w);
+  f.w2 = (f.w1 && !final64) ? f.w1 + c->nnode : nullptr;
+  f.w1f = (f.w1 && !final64) ? f.w1 + 2 * c->nnode : nullptr;
   return f;
 }
 
@@ -1288,7 +1291,8 @@ static Parts parts(const double *in, int nin, double *out, double *out2 = nullpt
 }
 
 template <typename T, int MODE>
-static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, int kid, IterState *its = nullptr) {
+static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, int kid, IterState *its = nullptr,
+                    const float *xf = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfLaunch ps(c, kid);
@@ -1297,7 +1301,7 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, in
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     MAG_TIMED_LAUNCH(ps, (film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
                        c->d_flags, f.S, f.twM, f.twN, G, hde, pp, its ? its : c->d_it,
-                       ((MODE == 0 || MODE == 5) && pp.out) ? (const T *)f.w1 : (const T *)nullptr);
+                       ((MODE == 0 || MODE == 3 || MODE == 5) && pp.out) ? (const T *)f.w1 : (const T *)nullptr, xf);
   });
   return MAG_OK;
 }
@@ -1393,11 +1397,12 @@ static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
 
 // The returned dg/dt of a MAG_MIXED_FINAL64 right-hand side: (11) once more
 // in double from the float iterate H the iteration stopped at,
-// gdot = K1 (H - dh_e) - C with C the free-space mean (Sec. 2.2), written to
-// out (which also holds H - dh_e in between).  The double spectrum reuses the
-// spectrum buffer, free once the iteration has stopped.  Enqueued only.
+// gdot = K1 (H - dh_e) - C, with C the free-space mean of K1 (H - dh_e)
+// (Sec. 2.2) taken as <w1, H - dh_e> / #out.  Three passes: R2C rows of
+// H - dh_e with the w1 sums, the 2/|k| column pass, C2R rows writing
+// gdot to out.  The double spectrum reuses the spectrum buffer, free once
+// the iteration has stopped.  Enqueued only.
 static int film_final64(mag_ctx *c, double *out) {
-  const long long n = c->nnode;
   const PartRegions pr = film_regions<float>(c);
   double *part = pr.F + pr.nb;   // after the regions of the float iteration
   const int nb64 = film_row_blocks<double>(c);
@@ -1405,21 +1410,14 @@ static int film_final64(mag_ctx *c, double *out) {
   {
     ProfScope ps(c, K_FILM_FINAL64);
     hipLaunchKernelGGL(final64_gate_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->d_it64);
-    hipLaunchKernelGGL(final64_lift_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                       reinterpret_cast<const float *>(c->d_H), out, n, c->d_it, c->d_it64);
   }
   int rc;
-  if ((rc = film_fwd<double, 2>(c, nullptr, out, 0.0, parts(nullptr, 0, nullptr), K_FILM_FINAL64, c->d_it64)))
+  if ((rc = film_fwd<double, 3>(c, nullptr, nullptr, 0.0, parts(nullptr, 0, part), K_FILM_FINAL64, c->d_it64,
+                                reinterpret_cast<const float *>(c->d_H))))
     return rc;
   if ((rc = film_col<double>(c, 0, parts(nullptr, 0, nullptr), c->d_it64, K_FILM_FINAL64))) return rc;
-  if ((rc = film_inv<double, 6>(c, nullptr, out, 0.0, parts(nullptr, 0, part), K_FILM_FINAL64, c->d_it64)))
+  if ((rc = film_inv<double, 6>(c, nullptr, out, 0.0, parts(part, nb64, nullptr), K_FILM_FINAL64, c->d_it64)))
     return rc;
-  {
-    ProfScope ps(c, K_FILM_FINAL64);
-    const long long per = 256LL * kFinal64Npt;
-    hipLaunchKernelGGL(final64_sub_mean_k, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, c->stream, out, n,
-                       (const double *)part, nb64, c->nout > 0 ? 1.0 / (double)c->nout : 0.0, c->d_it64);
-  }
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
@@ -1731,6 +1729,7 @@ int film_alloc(mag_ctx *c) {
   if (c->prec == MAG_MIXED_FINAL64) {
     MAG_HIP(c, hipMalloc(&c->d_it64, sizeof(IterState)));
     MAG_HIP(c, hipMemsetAsync(c->d_it64, 0, sizeof(IterState), c->stream));
+    MAG_HIP(c, hipMalloc(&c->d_w64, n * sizeof(double)));
   }
   // |k|^2 per axis: k = 2 pi fftfreq(n, d)
   const int nx = c->n[0], ny = c->n[1];
@@ -1793,6 +1792,23 @@ static int film_weights_t(mag_ctx *c, double *tmp) {
   return MAG_OK;
 }
 
+// w1 = K1 1_out in double for the final evaluation of a MAG_MIXED_FINAL64
+// context (tmp as for film_weights_t).
+static int film_weights64(mag_ctx *c, double *tmp) {
+  const long long n = c->nnode;
+  IterState is{};
+  int rc;
+  if ((rc = run_iter_init(c, is))) return rc;
+  if ((rc = film_fwd<double, 2>(c, nullptr, tmp, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
+  if ((rc = film_col<double>(c, 0))) return rc;
+  if ((rc = film_inv<double, 2>(c, nullptr, tmp + n, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
+  ProfScope ps(c, K_MISC);
+  hipLaunchKernelGGL((weights_k<double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, tmp + n,
+                     c->d_w64, c->d_flags, 0, n);
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
 int film_domain(mag_ctx *c) {
   const int nx = c->n[0], ny = c->n[1];
   const long long n = c->nnode;
@@ -1824,7 +1840,8 @@ int film_domain(mag_ctx *c) {
   double *tmp = nullptr;
   MAG_HIP(c, hipMalloc(&tmp, 2 * n * sizeof(double)));
   MAG_HIP(c, hipMemcpy(tmp, ind.data(), n * sizeof(double), hipMemcpyHostToDevice));
-  const int rc = c->prec == MAG_FP64 ? film_weights_t<double>(c, tmp) : film_weights_t<float>(c, tmp);
+  int rc = c->prec == MAG_FP64 ? film_weights_t<double>(c, tmp) : film_weights_t<float>(c, tmp);
+  if (!rc && c->prec == MAG_MIXED_FINAL64) rc = film_weights64(c, tmp);
   if (rc) {
     (void)hipFree(tmp);
     return rc;

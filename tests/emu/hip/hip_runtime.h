@@ -53,6 +53,7 @@ struct dim3 {
 };
 struct uint3v { unsigned x, y, z; };
 struct double2 { double x, y; };
+struct float2 { float x, y; };
 
 namespace emu {
 inline thread_local dim3 tIdx, bIdx;
