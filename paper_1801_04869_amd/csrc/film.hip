@@ -26,8 +26,13 @@ namespace mag {
 namespace {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
-__device__ __forceinline__ float inv_sqrt(float x) { return rsqrtf(x); }
+// Square roots of the Fourier multipliers: in float the bare hardware
+// instructions (within 1 ulp for the normal, positive |k|^2 they take),
+// in double the correctly rounded library functions.
+__device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float mult_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double mult_sqrt(double x) { return sqrt(x); }
 
 struct FilmGeom {
   int nx, ny, kx;
@@ -765,7 +770,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // MODE 5: write the value; sums over free space, and sums of |value| over D
 //         (second half of part).
 // Final double evaluation:
-// MODE 6: write value - C (double), C = (sum of pp.in) / #out.
+// MODE 6: write gdot = value - C (double), C = (sum of pp.in) / #out; with
+//         pp.out, sums of |gdot| over free space.
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -847,16 +853,20 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           if (out) acc += (double)val[e];
           acc2 += fabs((double)val[e]);
         } else if constexpr (MODE == 6) {
-          xd[ro + p] = (double)val[e] - cmean;
+          const double gd = (double)val[e] - cmean;
+          xd[ro + p] = gd;
+          if (out) acc += fabs(gd);
         } else {
           xd[ro + p] = hde + (double)val[e];
         }
       }
     }
   }
-  if constexpr (MODE != 2 && MODE != 6) {
-    const double sblk = block_total<RS::THREADS>(acc, red);
-    if (threadIdx.x == 0) pp.out[blk] = sblk;
+  if constexpr (MODE != 2) {
+    if (MODE != 6 || pp.out) {   // uniform over the block
+      const double sblk = block_total<RS::THREADS>(acc, red);
+      if (threadIdx.x == 0) pp.out[blk] = sblk;
+    }
   }
   if constexpr (MODE == 5) {
     const double sblk2 = block_total<RS::THREADS>(acc2, red + RS::THREADS / 64);
@@ -937,7 +947,7 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   const T c1 = (T)(2.0 * inv_n), c2 = (T)(0.5 * inv_n);
   auto mult = [&](T kk2) -> T {
     if (which == 0) return kk2 > (T)0 ? c1 * inv_sqrt(kk2) : (T)0;
-    return c2 * sqrt(kk2);
+    return c2 * mult_sqrt(kk2);
   };
   if (pair_block) {
     __syncthreads();   // the transform's last LDS reads are done
@@ -978,17 +988,41 @@ __global__ void __launch_bounds__(256) film_out(const T *__restrict__ Gm, double
   if (i < n) out[i] = (double)Gm[i] - it->C;
 }
 
-// Final evaluation of a MAG_MIXED_FINAL64 right-hand side.  Its kernels run
-// once the float iteration has stopped after at least one evaluation (a
-// stop, the fixed count reached, or a non-finite residual); the launches of
-// an unfinished block of iterations, or of a step that has reached its end
-// time, return at once.  gate->done is their skip flag; dh_e/dt and 1/#out
-// are copied from the iteration state.
-__global__ void __launch_bounds__(64) final64_gate_k(const IterState *__restrict__ it, IterState *__restrict__ gate) {
+// Final evaluation of a MAG_MIXED_FINAL64 right-hand side.  gate->done is
+// the skip flag of its kernels; dh_e/dt and 1/#out are copied from the
+// iteration state.
+// decide = 0 (stop test, or a fixed count of one): it runs once the float
+//   iteration has stopped after at least one evaluation (a stop, the count
+//   reached, or a non-finite residual); the launches of an unfinished block
+//   of iterations return at once.
+// decide = 1 (fixed count of two or more): the float iteration has skipped
+//   its last evaluation, and this one takes the decision in its place; it
+//   runs unless the iteration has already stopped (a non-finite residual).
+// Either way nothing runs in a step that has reached its end time.
+__global__ void __launch_bounds__(64) final64_gate_k(const IterState *__restrict__ it, IterState *__restrict__ gate,
+                                                     int decide) {
   if (threadIdx.x == 0) {
-    gate->done = (it->done && it->iters > 0) ? 0 : 1;
+    gate->done = decide ? (it->done ? 1 : 0) : ((it->done && it->iters > 0) ? 0 : 1);
     gate->hde = it->hde;
     gate->inv_nout = it->inv_nout;
+  }
+}
+
+// The decision after the final evaluation at a fixed count: residual mean of
+// |gdot| over free space from the per-block sums, the count, done (2 for a
+// non-finite residual, which also sets the sticky failure flag).
+__global__ void __launch_bounds__(64) final64_decide_k(const double *__restrict__ part, int np,
+                                                       IterState *__restrict__ it, IterState *mirror,
+                                                       const IterState *__restrict__ gate, int iters) {
+  if (gate->done) return;
+  const double r = parts_sum(part, np) * gate->inv_nout;
+  if (threadIdx.x == 0) {
+    const int done = isfinite(r) ? 1 : 2;
+    it->r = r;
+    it->iters = iters;
+    it->done = done;
+    if (done == 2) it->fail = 1;
+    *mirror = *it;
   }
 }
 
@@ -1378,8 +1412,13 @@ static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)
 // At a fixed count the last evaluation writes gdot to `out` itself and the
 // update that no evaluation would use is not launched (the column pass still
 // records the residual and the count); otherwise G is kept for film_out.
+// MAG_MIXED_FINAL64 at a fixed count of two or more: the last evaluation of
+// (11) is the double one of film_final64, which also takes the decision.
+static bool final64_decides(const mag_ctx *c) { return c->prec == MAG_MIXED_FINAL64 && c->fixed_iters >= 2; }
+
 template <typename T>
 static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
+  if (final64_decides(c) && i == c->fixed_iters - 1) return MAG_OK;
   const FilmPtrs<T> f = fptrs<T>(c);
   const PartRegions pr = film_regions<T>(c);
   int rc;
@@ -1400,24 +1439,34 @@ static int film_iteration(mag_ctx *c, double hde, int i, int nbs, double *out) {
 // gdot = K1 (H - dh_e) - C, with C the free-space mean of K1 (H - dh_e)
 // (Sec. 2.2) taken as <w1, H - dh_e> / #out.  Three passes: R2C rows of
 // H - dh_e with the w1 sums, the 2/|k| column pass, C2R rows writing
-// gdot to out.  The double spectrum reuses the spectrum buffer, free once
-// the iteration has stopped.  Enqueued only.
+// gdot to out.  At a fixed count of two or more it stands in for the float
+// iteration's last evaluation and takes the decision (final64_decide_k).
+// The double spectrum reuses the spectrum buffer, which the float iteration
+// no longer needs.  Enqueued only.
 static int film_final64(mag_ctx *c, double *out) {
   const PartRegions pr = film_regions<float>(c);
-  double *part = pr.F + pr.nb;   // after the regions of the float iteration
   const int nb64 = film_row_blocks<double>(c);
-  if (part + nb64 > c->d_part + c->npart) return set_error(c, MAG_E_STATE, "partial-sum buffer too small");
+  double *part = pr.F + pr.nb;   // after the regions of the float iteration: w1 sums
+  double *rpart = part + nb64;   // |gdot| sums
+  if (rpart + nb64 > c->d_part + c->npart) return set_error(c, MAG_E_STATE, "partial-sum buffer too small");
+  const int decide = final64_decides(c) ? 1 : 0;
   {
     ProfScope ps(c, K_FILM_FINAL64);
-    hipLaunchKernelGGL(final64_gate_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->d_it64);
+    hipLaunchKernelGGL(final64_gate_k, dim3(1), dim3(64), 0, c->stream, c->d_it, c->d_it64, decide);
   }
   int rc;
   if ((rc = film_fwd<double, 3>(c, nullptr, nullptr, 0.0, parts(nullptr, 0, part), K_FILM_FINAL64, c->d_it64,
                                 reinterpret_cast<const float *>(c->d_H))))
     return rc;
   if ((rc = film_col<double>(c, 0, parts(nullptr, 0, nullptr), c->d_it64, K_FILM_FINAL64))) return rc;
-  if ((rc = film_inv<double, 6>(c, nullptr, out, 0.0, parts(part, nb64, nullptr), K_FILM_FINAL64, c->d_it64)))
+  if ((rc = film_inv<double, 6>(c, nullptr, out, 0.0, parts(part, nb64, decide ? rpart : nullptr), K_FILM_FINAL64,
+                                c->d_it64)))
     return rc;
+  if (decide) {
+    ProfScope ps(c, K_FILM_FINAL64);
+    hipLaunchKernelGGL(final64_decide_k, dim3(1), dim3(64), 0, c->stream, (const double *)rpart, nb64, c->d_it,
+                       c->h_it, (const IterState *)c->d_it64, c->fixed_iters);
+  }
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }

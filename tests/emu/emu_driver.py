@@ -157,7 +157,9 @@ def main(path, which):
                   ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 1, 3),
                   # mixed iteration with the final evaluation in double
                   ("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 2, 2),
-                  ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 2, 3)]
+                  ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 2, 3),
+                  ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 2, 1),
+                  ("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 2, 0)]
     for name, case, prec, fixed in cases:
         h, keep = setup(L, case, prec, fixed=fixed)
         rc, it, out = run_rhs(L, h, case["state"], 0.2)
@@ -166,7 +168,9 @@ def main(path, which):
         ref, rit, rst = mod.rhs(prob, case["state"], 0.2)
         err = rel_l2(out, ref)
         tol = 1e-10 if prec == 0 else 1e-4
-        ok = rc == 0 and it == fixed and err < tol
+        if fixed == 0 and it != rit:
+            tol = 10 * 2e-4   # a mixed form may stop one evaluation apart from the oracle
+        ok = rc == 0 and (it == fixed if fixed else it >= 1) and err < tol
         fails += not ok
         print("%-10s n=%s prec=%d fixed=%d rc=%d it=%d rel-L2=%.3e %s" % (name, case["n"], prec, fixed, rc, it, err,
                                                                          "ok" if ok else "FAIL"), flush=True)

@@ -271,6 +271,9 @@ inline hipError_t hipMalloc(void *p, size_t n) {
 template <typename T>
 inline hipError_t hipMallocAsync(T **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
 inline float rsqrtf(float x) { return 1.0f / std::sqrt(x); }
+// the bare gfx950 square-root instructions (1 ulp there; correctly rounded here)
+#define __builtin_amdgcn_rsqf(x) (1.0f / std::sqrt((float)(x)))
+#define __builtin_amdgcn_sqrtf(x) std::sqrt((float)(x))
 #define __align__(n) alignas(n)
 #define MAG_OPAQUE(x) asm volatile("" : "+m"(x))
 #define MAG_WAVES_PER_EU(...)
