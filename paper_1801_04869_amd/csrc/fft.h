@@ -162,6 +162,17 @@ constexpr int plan_ns() {
   return ns;
 }
 
+// Work-group barrier for the LDS exchanges of the transforms: its fences are
+// limited to the local address space, so the wave's outstanding global loads
+// and stores need not complete first (a plain __syncthreads waits for every
+// outstanding vector-memory operation, which would serialise a transform
+// with the loads issued for the next one).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // One pencil transform.  v[RMAX] holds x[j + rho*TT] on entry and X[j + rho*TT]
 // on exit.  lre/lim: this pencil's LDS scratch (real and imaginary planes),
 // element i at offset lidx(i).  tw: exp(-2 pi i m / N), m = 0..N-1.
@@ -170,20 +181,20 @@ template <int N, int DIR, typename P = Plan<N>, typename T, typename LIdx>
 __device__ __forceinline__ void pencil_fft(cx<T>* v, int j, T* lre, T* lim, LIdx lidx,
                                            const cx<T>* __restrict__ tw) {
   constexpr int RMAX = P::RMAX, TT = P::TT, S = P::S;
-  if constexpr (S > 1) __syncthreads();   // LDS may still be read by a previous use
+  if constexpr (S > 1) lds_barrier();   // LDS may still be read by a previous use
   static_for<0, S>([&](auto sI) {
     constexpr int s = decltype(sI)::value;
     constexpr int R = P::R[s];
     constexpr int U = RMAX / R;
     constexpr int Ns = plan_ns<P, s>();
     if constexpr (s > 0) {
-      __syncthreads();
+      lds_barrier();
 #pragma unroll
       for (int rho = 0; rho < RMAX; ++rho) {
         const int o = lidx(j + rho * TT);
         v[rho] = {lre[o], lim[o]};
       }
-      if constexpr (s < S - 1) __syncthreads();
+      if constexpr (s < S - 1) lds_barrier();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -294,17 +305,17 @@ __device__ __forceinline__ cx<T> tw_get(const TwPre<PL, T, LOCAL>& t, int u, int
 template <int N, int DIR, typename P = Plan<N>, typename T, typename LIdx, typename TW>
 __device__ __forceinline__ void pencil_fft_cx(cx<T>* v, int j, cx<T>* lds, LIdx lidx, const TW& tw) {
   constexpr int RMAX = P::RMAX, TT = P::TT, S = P::S;
-  if constexpr (S > 1) __syncthreads();   // LDS may still be read by a previous use
+  if constexpr (S > 1) lds_barrier();   // LDS may still be read by a previous use
   static_for<0, S>([&](auto sI) {
     constexpr int s = decltype(sI)::value;
     constexpr int R = P::R[s];
     constexpr int U = RMAX / R;
     constexpr int Ns = plan_ns<P, s>();
     if constexpr (s > 0) {
-      __syncthreads();
+      lds_barrier();
 #pragma unroll
       for (int rho = 0; rho < RMAX; ++rho) v[rho] = lds[lidx(j + rho * TT)];
-      if constexpr (s < S - 1) __syncthreads();
+      if constexpr (s < S - 1) lds_barrier();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {

@@ -159,7 +159,10 @@ def main(path, which):
                   ("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 2, 2),
                   ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 2, 3),
                   ("film", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 2, 1),
-                  ("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 2, 0)]
+                  ("film", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 2, 0),
+                  # column passes of 1024 and 2048 rows: two column groups per block
+                  ("film", film_case(16, 1024, L=(0.25, 2.0), kind="offrect", jc_s=0.2), 1, 2),
+                  ("film", film_case(16, 2048, L=(0.25, 2.0), kind="offrect", jc_s=0.2), 0, 1)]
     for name, case, prec, fixed in cases:
         h, keep = setup(L, case, prec, fixed=fixed)
         rc, it, out = run_rhs(L, h, case["state"], 0.2)

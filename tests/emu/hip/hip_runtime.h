@@ -69,6 +69,11 @@ inline unsigned char *dyn = nullptr;
 #define HIP_DYNAMIC_SHARED(type, var) type *var = reinterpret_cast<type *>(emu::dyn);
 
 inline void __syncthreads() { emu::bar->arrive_and_wait(); }
+// the barrier and fence builtins (the emulated work-items are threads whose
+// block barrier already orders every memory access)
+#define __builtin_amdgcn_s_barrier() __syncthreads()
+#define __builtin_amdgcn_fence(...) ((void)0)
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
 
 // Cross-lane exchange within a 64-wide wavefront, emulated through a per-block
 // buffer between two block barriers (all work-items of the block must call it

@@ -99,22 +99,27 @@ def test_mixed_final64_form_error_per_result_converged():
         assert v < 1e-4, k
 
 
-def test_mixed_form_error_per_result_converged():
+@pytest.fixture(scope="module")
+def mixed_converged_errors():
+    mat, jc = _ring()
+    return _errors(mat, jc, np.zeros((N, N)), 0.0, 0, 2e-4, t_end=0.005)
+
+
+def test_mixed_form_error_per_result_converged(mixed_converged_errors):
     """A trajectory from the virgin state (258 steps to t = 0.005) with the
     converged inner iteration, MAG_MIXED.  The per-right-hand-side difference
     at the end state stays within the mixed form's tolerance.  The
     per-result differences carry the rounding of the FP32 evaluation of (11)
     that produces each returned dg/dt along the trajectory (measured: g 3e-5,
-    h_z 9e-4, j 1.3e-3, m 2e-7; with that evaluation in double, the test
-    above, they fall below 5e-6).  The bound is five times the largest
-    measured difference, far below what a wrong term in the mixed path gives
-    (order one)."""
-    mat, jc = _ring()
-    g0 = np.zeros((N, N))
-    e = _errors(mat, jc, g0, 0.0, 0, 2e-4, t_end=0.005)
-    for k, v in e.items():
+    h_z 1e-3, j 1.5e-3, m 2e-7; with that evaluation in double, the test
+    above, they fall below 5e-6).  This bound is five times the largest
+    measured difference, a regression guard far below what a wrong term in
+    the mixed path gives (order one); the 1e-4 bound is the xfail below."""
+    for k, v in mixed_converged_errors.items():
         assert v < 7e-3, k
     # one right-hand side at the end state of the FP64 run, both forms
+    mat, jc = _ring()
+    g0 = np.zeros((N, N))
     c64, c32 = _ctx(api.FP64, mat, jc, 0), _ctx(api.MIXED, mat, jc, 0)
     grid, y = _grid(c64, g0, 0.0, t_end=0.005)
     t = grid[-1][0] + grid[-1][1]
@@ -123,3 +128,11 @@ def test_mixed_form_error_per_result_converged():
     d = (torch.linalg.norm(o32 - o64) / torch.linalg.norm(o64)).item()
     print("right-hand side at the end state: rel-L2 mixed vs FP64 %.2e" % d, flush=True)
     assert d < 1e-4
+
+
+@pytest.mark.xfail(strict=True, reason="MAG_MIXED: the FP32 evaluation of (11) that produces each returned dg/dt "
+                                       "puts h_z and j about 1e-3 from FP64 after 258 converged steps; "
+                                       "MAG_MIXED_FINAL64 meets 1e-4")
+def test_mixed_form_within_1e4_per_result_converged(mixed_converged_errors):
+    for k in ("hz", "j", "m"):
+        assert mixed_converged_errors[k] < 1e-4, k
