@@ -23,8 +23,8 @@ Discretisation (the staggered finite-difference form of the method of lines):
 Iteration (10)-(12) with the Fourier multipliers 2/|k| (eq. (7)) and |k|/2
 (eq. (12)), both zero at k = 0, on the FFT grid k = 2 pi fftfreq(n, d).  The
 update (12) may carry the Gaussian filter exp(-|k|^2 sigma^2 / 2) that Sec.
-2.2 applies to its spectral derivatives and, in the same way, to (12)
-(``sigma``; the paper's value is sqrt(dx^2 + dy^2), see ``paper_sigma``).
+2.2 applies to its spectral derivatives and also to (12) (``sigma``; the
+paper's value is sqrt(dx^2 + dy^2), see ``paper_sigma``).
 The staggered form leaves it off by default (sigma = 0): with unsmoothed
 finite differences inside the film the filtered update cannot correct the
 high-|k| part of the free-space error and the residual stalls.  The filter

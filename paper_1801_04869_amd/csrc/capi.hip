@@ -370,8 +370,8 @@ __global__ void __launch_bounds__(256) rk_errnorm_sc_k(const double *__restrict_
 }
 
 // Accept or reject the attempt: error norm = max of the block maxima; a
-// failed stage (non-finite residual, sticky flag) rejects with h / 2 (the
-// paper's "huge gdot" device, Sec. 2.2); otherwise the controller of the
+// failed stage (non-finite residual, sticky flag) rejects with h / 2 (Sec.
+// 2.2 reduces the step when gdot blows up); otherwise the controller of the
 // host-driven step.  Then the end-time clip and the underflow check that the
 // host loop applies before an attempt.
 __global__ void __launch_bounds__(256) step_accept_k(StepCtl *sc, StepCtl *mirror, const double *__restrict__ part,
