@@ -342,7 +342,10 @@ __global__ void __launch_bounds__(256) rk_axpy_sc_k(double *__restrict__ out, co
   out[i] = y[i] + h * s;
 }
 
-// Per-block max of the scaled error (as rk_errnorm_k), h, rtol and atol from the step record.
+// Per-block max of the scaled error (as rk_errnorm_k), h, rtol and atol from
+// the step record.  kErrNpt entries per work-item, 256 apart, so that the
+// accept kernel has few block maxima to combine.
+constexpr int kErrNpt = 8;
 __global__ void __launch_bounds__(256) rk_errnorm_sc_k(const double *__restrict__ k1, const double *__restrict__ k2,
                                                        const double *__restrict__ k3, const double *__restrict__ k4,
                                                        double e1, double e2, double e3, double e4,
@@ -352,13 +355,18 @@ __global__ void __launch_bounds__(256) rk_errnorm_sc_k(const double *__restrict_
   __shared__ double sh[256];
   if (sc->finished) return;
   const double h = sc->h, rtol = sc->rtol, atol = sc->atol;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long i0 = (long long)blockIdx.x * (256 * kErrNpt) + threadIdx.x;
   double v = 0.0;
-  if (i < n) {
-    const double err = h * (e1 * k1[i] + e2 * k2[i] + e3 * k3[i] + e4 * k4[i]);
-    const double sc_ = fmax(rtol * fmax(fabs(y[i]), fabs(yn[i])), atol);
-    v = fabs(err) / sc_;
-    if (!isfinite(v)) v = INFINITY;
+#pragma unroll
+  for (int u = 0; u < kErrNpt; ++u) {
+    const long long i = i0 + (long long)u * 256;
+    if (i < n) {
+      const double err = h * (e1 * k1[i] + e2 * k2[i] + e3 * k3[i] + e4 * k4[i]);
+      const double sc_ = fmax(rtol * fmax(fabs(y[i]), fabs(yn[i])), atol);
+      double w = fabs(err) / sc_;
+      if (!isfinite(w)) w = INFINITY;
+      v = fmax(v, w);
+    }
   }
   sh[threadIdx.x] = v;
   __syncthreads();
@@ -384,8 +392,15 @@ __global__ void __launch_bounds__(256) step_accept_k(StepCtl *sc, StepCtl *mirro
     }
     return;
   }
+  // eight block maxima in flight per work-item
   double m = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) m = fmax(m, part[i]);
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 256 * 8) {
+    double w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = i0 + u * 256 < nb ? part[i0 + u * 256] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fmax(m, w[u]);
+  }
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -1132,9 +1147,10 @@ static int enqueue_attempt(mag_ctx *c, double *state) {
     if (int rc = film_rhs_enqueue(c, st[s].y, st[s].k)) return rc;
   }
   ProfScope ps(c, K_RK);
-  hipLaunchKernelGGL(rk_errnorm_sc_k, dim3(nbe), dim3(256), 0, c->stream, k1, k2, k3, k4, kE1, kE2, kE3, kE4, state,
+  const unsigned nbr = (unsigned)((n + 256 * kErrNpt - 1) / (256 * kErrNpt));
+  hipLaunchKernelGGL(rk_errnorm_sc_k, dim3(nbr), dim3(256), 0, c->stream, k1, k2, k3, k4, kE1, kE2, kE3, kE4, state,
                      yn, c->d_sc, n, c->d_red);
-  hipLaunchKernelGGL(step_accept_k, dim3(1), dim3(256), 0, c->stream, c->d_sc, c->h_sc, c->d_red, (int)nbe, c->d_it);
+  hipLaunchKernelGGL(step_accept_k, dim3(1), dim3(256), 0, c->stream, c->d_sc, c->h_sc, c->d_red, (int)nbr, c->d_it);
   hipLaunchKernelGGL(step_commit_k, dim3(nbe), dim3(256), 0, c->stream, state, yn, k1, k4, c->d_sc, n);
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
