@@ -36,6 +36,8 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert L.mag_create(None, 3, 0, None) == -1
     assert L.mag_create(ctypes.byref(h), 4, 0, None) == -1
     assert L.mag_create(ctypes.byref(h), 3, 7, None) == -1
+    # the final-FP64-evaluation form is a film form
+    assert L.mag_create(ctypes.byref(h), 3, 2, None) == -1
     assert not h.value
     assert L.mag_last_error(None) == b"null context"
     assert L.mag_set_grid(None, 16, 16, 16, 1.0, 1.0, 1.0) == -1
@@ -43,3 +45,19 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert L.mag_prof_kernel_name(0) is not None
     assert L.mag_prof_kernel_name(10 ** 6) is None
     L.mag_destroy(None)
+
+
+def test_python_constants_match_the_header():
+    """Status codes, precisions and field kinds of the binding are the
+    enumerators of include/magfft.h."""
+    import re
+    from paper_1801_04869_amd import api
+    txt = open(_lib.HEADER).read()
+    enum = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(MAG_[A-Z0-9_]+)\s*=\s*(-?\d+)", txt)}
+    pairs = {"OK": "MAG_OK", "NOT_CONVERGED": "MAG_NOT_CONVERGED", "STEP_UNDERFLOW": "MAG_STEP_UNDERFLOW",
+             "E_ARG": "MAG_E_ARG", "E_STATE": "MAG_E_STATE", "E_HIP": "MAG_E_HIP", "E_NOMEM": "MAG_E_NOMEM",
+             "E_NUMERIC": "MAG_E_NUMERIC", "FP64": "MAG_FP64", "MIXED": "MAG_MIXED",
+             "MIXED_FINAL64": "MAG_MIXED_FINAL64", "RAMP": "MAG_FIELD_RAMP", "SINE": "MAG_FIELD_SINE",
+             "ROTATE": "MAG_FIELD_ROTATE"}
+    for py, c in pairs.items():
+        assert getattr(api, py) == enum[c], (py, c)
