@@ -250,6 +250,49 @@ def run_gpu(prec, wl, mat, jc, g, steps, warmup, t, fixed=0, lam=0.7):
     return res
 
 
+def gradient_run(prec, wl, mat, jc, g_snap, t_snap, lam, iters, n_steps=32, every=16):
+    """The h_z misfit gradient with respect to the per-cell jc map along a
+    trajectory (checkpointed reverse driver, autograd.trajectory): the
+    accepted step sizes of an adaptive run from the Bean-like snapshot are
+    replayed from the same start (fixed inner count, every right-hand side
+    from h_e), with a checkpoint every `every` steps; the loss is
+    1/2 sum (h_z - 0)^2 dx dy at the last step.  Times the forward trajectory
+    and the backward pass.  (From the snapshot the power law is active in the
+    whole film, so the steps are short but the gradient is not zero, as it
+    would be from g = 0, where |j| << jc makes rho(|j|) vanish.)"""
+    import torch
+    from paper_1801_04869_amd import autograd as ag
+    ctx = make_ctx(prec, wl, mat, jc, iters, lam=lam)
+    nx, ny = wl["n"]
+    y = torch.from_numpy(g_snap).cuda()
+    t, h, steps, attempts = t_snap, 1e-15, [], 0
+    while len(steps) < n_steps:
+        t1, h1, acc = ctx.step(y, t, h)
+        if acc:
+            steps.append(h)
+        t, h = t1, h1
+        attempts += 1
+        assert attempts < 20 * n_steps, "adaptive run keeps rejecting"
+    g0 = torch.from_numpy(g_snap).cuda()
+    jc_t = torch.from_numpy(jc).cuda().requires_grad_(True)
+    dA = (2 * wl["L"][0] / nx) * (2 * wl["L"][1] / ny)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    (yl,) = ag.trajectory(ctx, g0, jc_t, t_snap, steps, [n_steps - 1], every=every)
+    hz = ag.hz(ctx, yl, t_snap + sum(steps))
+    loss = 0.5 * (hz * hz).sum() * dA
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = jc_t.grad
+    ctx.close()
+    return dict(steps=n_steps, checkpoint_every=every, t_span=sum(steps), forward_ms=round(1e3 * (t1 - t0), 2),
+                backward_ms=round(1e3 * (t2 - t1), 2), backward_over_forward=round((t2 - t1) / (t1 - t0), 3),
+                grad_finite=bool(torch.isfinite(g).all()), grad_norm=float(torch.linalg.norm(g)))
+
+
 def converged_window(prec, wl, mat, jc, lam, warm_attempts, attempts):
     """Right-hand sides of an adaptive BS23 run with the stop test: from the
     virgin state g = 0 at t = 0, `warm_attempts` step attempts (untimed) bring
@@ -512,6 +555,15 @@ def main():
     line["bs23_captured"] = ("step control on the device, 32 attempts (%d accepted) from g = 0 at t = 0 replayed "
                              "from a captured graph of 16 attempts (one host synchronisation per replay); the "
                              "first right-hand side and step size on the host" % m["captured_attempts"][0])
+    if not a.quick:
+        gr = gradient_run("mixed", wl, mat, jc, g, a.t, LAMBDA_2048[a.mask], a.iters)
+        gr["workload"] = ("film-2048-%s, mixed, %d inner iterations: h_z misfit gradient with respect to the jc map "
+                          "over %d replayed adaptive steps from the Bean-like snapshot at t = %g, checkpoints "
+                          "every %d steps" % (a.mask, a.iters, gr["steps"], a.t, gr["checkpoint_every"]))
+        line["film_2048_gradient"] = gr
+        print("[bench] film-2048-%s gradient: forward %.1f ms, backward %.1f ms (%.2fx), finite %s" %
+              (a.mask, gr["forward_ms"], gr["backward_ms"], gr["backward_over_forward"], gr["grad_finite"]),
+              file=sys.stderr, flush=True)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a.mask, a.t, a.iters)
         line["cpu_baseline"]["workload"] = film_workload
