@@ -293,6 +293,23 @@ def gradient_run(prec, wl, mat, jc, g_snap, t_snap, lam, iters, n_steps=32, ever
                 grad_finite=bool(torch.isfinite(g).all()), grad_norm=float(torch.linalg.norm(g)))
 
 
+def observe_time(prec, wl, mat, jc, g, t, reps=20):
+    """Mean time of mag_observe (h_z by the |k|/2 transform of g, j on the
+    edges, the moment) on the snapshot, in ms."""
+    import torch
+    ctx = make_ctx(prec, wl, mat, jc, 4)
+    state = torch.from_numpy(g).cuda()
+    for _ in range(3):
+        ctx.observe(state, t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.observe(state, t)   # returns the moment on the host: synchronises
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return round(1e3 * dt / reps, 4)
+
+
 def converged_window(prec, wl, mat, jc, lam, warm_attempts, attempts):
     """Right-hand sides of an adaptive BS23 run with the stop test: from the
     virgin state g = 0 at t = 0, `warm_attempts` step attempts (untimed) bring
@@ -556,6 +573,7 @@ def main():
                              "from a captured graph of 16 attempts (one host synchronisation per replay); the "
                              "first right-hand side and step size on the host" % m["captured_attempts"][0])
     if not a.quick:
+        line["observe_ms"] = {p: observe_time(p, wl, mat, jc, g, a.t) for p in ("mixed", "fp64")}
         gr = gradient_run("mixed", wl, mat, jc, g, a.t, LAMBDA_2048[a.mask], a.iters)
         gr["workload"] = ("film-2048-%s, mixed, %d inner iterations: h_z misfit gradient with respect to the jc map "
                           "over %d replayed adaptive steps from the Bean-like snapshot at t = %g, checkpoints "
