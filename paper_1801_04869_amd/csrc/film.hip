@@ -26,6 +26,18 @@ namespace mag {
 namespace {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
+
+// LDS exchange slot of complex element i of a pencil: one padding element
+// after every 128 bytes (16 FP32 or 8 FP64 complex values); the pencil's
+// pitch in elements.
+template <typename T>
+__device__ __forceinline__ int lds_pad(int i) {
+  return sizeof(T) == 4 ? i + (i >> 4) : i + (i >> 3);
+}
+template <typename T>
+constexpr int lds_pitch(int n) {
+  return sizeof(T) == 4 ? n + n / 16 : n + n / 8;
+}
 // Square roots of the Fourier multipliers: in float the bare hardware
 // instructions (within 1 ulp for the normal, positive |k|^2 they take),
 // in double the correctly rounded library functions.
@@ -151,13 +163,13 @@ __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) ==
 // complex values per wavenumber k, P chosen so that this run is at least 32
 // bytes.  Consecutive row blocks are placed on the same XCD (see
 // xcd_block) so that the runs of neighbouring blocks meet in one L2.  The block's LDS holds either the FFT exchange of its P rows (pitch
-// M + M/16) or the transposed [M+1][P+1] tile of its output, one after the
+// lds_pitch<T>(M)) or the transposed [M+1][P+1] tile of its output, one after the
 // other.
 template <int M, typename T>
 struct FilmRowShape {
   using PL = Plan8<M>;
   static constexpr int TT = PL::TT;
-  static constexpr int PITCH = M + M / 16;
+  static constexpr int PITCH = lds_pitch<T>(M);
   static constexpr int PMIN = 32 / (2 * (int)sizeof(T));
   static constexpr int PT = 256 / TT > 0 ? 256 / TT : 1;
   static constexpr int P = PT > PMIN ? PT : PMIN;
@@ -210,7 +222,7 @@ struct FilmColShape {
   using PL = Plan8<NY>;
   static constexpr int TT = PL::TT;
   static constexpr int P = 256 / TT > 0 ? 256 / TT : 1;
-  static constexpr int PITCH = NY + NY / 16;
+  static constexpr int PITCH = lds_pitch<T>(NY);
   static constexpr int LDS_T = 2 * P * PITCH;
   static constexpr int THREADS = P * TT;
   static_assert(LDS_T * sizeof(T) <= 150 * 1024, "column block LDS too large");
@@ -431,7 +443,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   }
   row_tw_put(rtw, twM, twN);   // first read after the transform's entry barrier
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
-  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return lds_pad<T>(i); }, twM);
   // Half spectrum of the real row from the packed transform Z:
   // X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]), W = exp(-2 pi i / 2M).
   __syncthreads();
@@ -542,7 +554,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   }
   if constexpr (PL::S == 1) __syncthreads();
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
-  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return lds_pad<T>(i); }, twM);
   double acc = 0.0, acc2 = 0.0, acc3 = 0.0;
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
@@ -573,7 +585,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     }
     v[rho] = {u[0], u[1]};
   }
-  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return lds_pad<T>(i); }, twM);
   __syncthreads();
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) xch[j + rho * TT] = v[rho];
@@ -689,7 +701,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   }
   if constexpr (PL::S == 1) __syncthreads();
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
-  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return lds_pad<T>(i); }, twM);
   double acc = 0.0, acc2 = 0.0;
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
@@ -725,7 +737,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     }
     v[rho] = {u[0], u[1]};
   }
-  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  pencil_fft_cx<M, -1, PL>(v, j, xch, [](int i) { return lds_pad<T>(i); }, twM);
   __syncthreads();
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) xch[j + rho * TT] = v[rho];
@@ -820,7 +832,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   }
   if constexpr (PL::S == 1) __syncthreads();   // single-stage FFTs do not fence the tile
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
-  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return i + (i >> 4); }, twM);
+  pencil_fft_cx<M, +1, PL>(v, j, xch, [](int i) { return lds_pad<T>(i); }, twM);
   double acc = 0.0;
   if (active) {
 #pragma unroll
@@ -941,7 +953,7 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   // column's loads are issued (nothing is written before the test)
   if (!pp.in && it->done) return;
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
-  auto lidx = [](int i) { return i + (i >> 4); };
+  auto lidx = [](int i) { return lds_pad<T>(i); };
   pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, twp);
   // multiplier in the compute precision: |k|^2 = kx^2 + ky^2
   const T c1 = (T)(2.0 * inv_n), c2 = (T)(0.5 * inv_n);
