@@ -62,7 +62,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mask", default="ring", choices=["ring", "slot"], help="mask of the headline line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--quick", action="store_true", help="headline mask and mixed precision only")
+    ap.add_argument("--quick", action="store_true", help="headline mask and one precision only")
+    ap.add_argument("--quick-prec", default="mixed", choices=["mixed", "fp64", "final64"],
+                    help="the precision of a --quick run (profiling of one form)")
     ap.add_argument("--t", type=float, default=0.6, help="snapshot time")
     ap.add_argument("--iters", type=int, default=4, help="inner iterations per right-hand side")
     ap.add_argument("--window", type=int, default=20, help="timed BS23 attempts of the converged line")
@@ -492,7 +494,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     masks = [a.mask] if a.quick else [a.mask] + [m for m in ("ring", "slot") if m != a.mask]
-    precs = ["mixed"] if a.quick else ["mixed", "fp64", "final64"]
+    precs = [a.quick_prec] if a.quick else ["mixed", "fp64", "final64"]
+    hp = precs[0]   # precision of the roofline and kernel-table lines
     res = {}
     inputs = {}
     for mask in masks:
@@ -516,18 +519,18 @@ def main():
     nx, ny = wl["n"]
     n, kx = nx * ny, nx // 2 + 1
     n_out = free_nodes(mat)
-    m = res[(a.mask, "mixed")]
+    m = res[(a.mask, hp)]
     kern = m["dominant"]
     cnt, tot = m["prof_dom"]
     avg_s = tot / cnt * 1e-3
-    ab = alg_bytes(kern, n, kx, ny, "mixed", a.iters, n_out)
+    ab = alg_bytes(kern, n, kx, ny, hp, a.iters, n_out)
     achieved = ab / avg_s / 1e9
     film_workload = ("film-2048-%s: 1024^2-cell %s film in a 2048^2 periodic grid, n=30, log-normal jc (s=0.2, "
                      "l=8 cells), h_e=0.8 sin(1.25 t), Bean-like snapshot at t=%g; %d inner iterations per RHS"
                      % (a.mask, a.mask, a.t, a.iters))
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kern, "mixed"), kernel=kern,
-                bytes_per_launch=ab, avg_launch_us=round(avg_s * 1e6, 2), workload=film_workload + ", mixed")
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kern, hp), kernel=kern,
+                bytes_per_launch=ab, avg_launch_us=round(avg_s * 1e6, 2), workload=film_workload + ", " + hp)
     fixed_lines = {}
     for (mask, prec), r in res.items():
         fixed_lines["%s-%s" % (mask, prec)] = dict(value=round(r["value"], 3), unit="RHS evals/s",
@@ -540,14 +543,13 @@ def main():
                 data="synthetic",
                 config=dict(workload=UNMEASURED, measured="film-2048 (thin-film method), below"),
                 roofline=roof)
-    line["film_2048_fixed%d" % a.iters] = dict(workload=film_workload, lines=fixed_lines,
-                                               kernels_mixed=kernel_table(m["prof"], n, kx, ny, "mixed", a.iters,
-                                                                          n_out))
+    line["film_2048_fixed%d" % a.iters] = dict(workload=film_workload, lines=fixed_lines)
+    line["film_2048_fixed%d" % a.iters]["kernels_" + hp] = kernel_table(m["prof"], n, kx, ny, hp, a.iters, n_out)
     line["film_2048_converged"] = dict(
         workload="film-2048 ring/slot, adaptive BS23 (rtol 1e-3, atol 1e-6) from g = 0 at t = 0: %d untimed "
                  "attempts, then %d timed attempts; stop test 2e-4 max(|dh_e/dt|, 1), warm start, lambda %s"
                  % (a.warmup, a.window, LAMBDA_2048), lines=conv)
-    if (a.mask, "fp64") in res:
+    if (a.mask, "fp64") in res and hp == "mixed":
         f64 = res[(a.mask, "fp64")]
         line["mixed_over_fp64_fixed"] = round(m["value"] / f64["value"], 3)
         d = m["out"] - f64["out"]
