@@ -31,6 +31,18 @@ high-|k| part of the free-space error and the residual stalls.  The filter
 only preconditions the update: the converged gdot (zero in free space, eq.
 (10)) does not depend on it.  The post-processing h_z of Sec. 2.1 uses the
 plain |k|/2.
+
+Spectral form (``deriv="spectral"``, the paper's own discretisation of Sec.
+2.2): every field lives on the nodes; a derivative d/dx_a is the Fourier
+multiplier i k_a exp(-|k|^2 s^2 / 2), s = ``deriv_sigma`` (default the
+paper's sqrt(dx^2 + dy^2)), with the Nyquist wavenumber of that axis set to
+zero (an odd symbol there has no real counterpart).  j = (d_y g, -d_x g) at
+the nodes; e = rho(|j|) j with the power law at nodes whose four cells are
+superconducting (jc the mean of the four cells) and rho_out at every other
+node; dh_z/dt = -(d_x e_y - d_y e_x) at in-nodes.  The update (12) keeps
+its own filter ``sigma``, 0 by default in both forms: filtered, it stalls
+here too (a cold start at g = 0 on a 64^2 disk does not reach the stop
+test in 100 iterations; unfiltered it takes at most 7).
 """
 import numpy as np
 
@@ -57,7 +69,8 @@ class FilmProblem:
     """
 
     def __init__(self, nx, ny, Lx, Ly, material, jc_cell=None, jc0=1.0, n=19.0, e0=1.0,
-                 rho_out=1.0, lam=0.7, tol=2e-4, max_inner=100, fixed_iters=0, field=None, sigma=0.0):
+                 rho_out=1.0, lam=0.7, tol=2e-4, max_inner=100, fixed_iters=0, field=None, sigma=0.0,
+                 deriv="staggered", deriv_sigma=None):
         self.nx, self.ny = int(nx), int(ny)
         self.Lx, self.Ly = float(Lx), float(Ly)
         self.dx, self.dy = 2.0 * self.Lx / self.nx, 2.0 * self.Ly / self.ny
@@ -68,8 +81,13 @@ class FilmProblem:
         self.lam, self.tol = float(lam), float(tol)
         self.max_inner, self.fixed_iters = int(max_inner), int(fixed_iters)
         self.field = field if field is not None else AppliedField()
-        # Gaussian filter of the update (12), Sec. 2.2 (None: the paper's sqrt(dx^2 + dy^2))
+        if deriv not in ("staggered", "spectral"):
+            raise ValueError(deriv)
+        self.deriv = deriv
+        # Gaussian filters, Sec. 2.2 (None: the paper's sqrt(dx^2 + dy^2)):
+        # sigma of the update (12), deriv_sigma of the spectral derivatives
         self.sigma = float(paper_sigma(self.dx, self.dy) if sigma is None else sigma)
+        self.deriv_sigma = float(paper_sigma(self.dx, self.dy) if deriv_sigma is None else deriv_sigma)
         self.warm = None
         self._classify()
         self._symbols()
@@ -89,6 +107,11 @@ class FilmProblem:
         # y-edge (p+1/2, q) separates cells (p, q-1) and (p, q)
         self.sc_yedge = sc & shift(sc, 0, -1)
         self.jc_yedge = 0.5 * (self.jc_cell + shift(self.jc_cell, 0, -1))
+        # spectral form: a node is superconducting when its four cells are,
+        # with jc the mean of the four cells
+        self.sc_node = sc & shift(sc, 1, -1) & shift(sc, 0, -1) & shift(shift(sc, 1, -1), 0, -1)
+        jc = self.jc_cell
+        self.jc_node = 0.25 * (jc + shift(jc, 1, -1) + shift(jc, 0, -1) + shift(shift(jc, 1, -1), 0, -1))
 
     def _symbols(self):
         """Multipliers of eqs. (7) and (12) on the FFT grid (angular wavenumbers)."""
@@ -100,7 +123,18 @@ class FilmProblem:
         self.K1[nz] = 2.0 / kabs[nz]          # eq. (7): 2/|k|, set to 0 at k = 0
         self.K2 = 0.5 * kabs                  # |k|/2 (0 at k = 0): h_z of Sec. 2.1
         # eq. (12) with the Gaussian smoothing of Sec. 2.2
-        self.K2s = self.K2 * np.exp(-0.5 * (self.sigma * kabs) ** 2)
+        gauss = np.exp(-0.5 * (self.sigma * kabs) ** 2)
+        self.K2s = self.K2 * gauss
+        # spectral derivatives: i k_a exp(-|k|^2 s^2 / 2), Nyquist of axis a zeroed
+        dgauss = np.exp(-0.5 * (self.deriv_sigma * kabs) ** 2)
+        kxn = kx.copy()
+        kyn = ky.copy()
+        if self.nx % 2 == 0:
+            kxn[self.nx // 2] = 0.0
+        if self.ny % 2 == 0:
+            kyn[self.ny // 2] = 0.0
+        self.DX = 1j * kxn[None, :] * dgauss
+        self.DY = 1j * kyn[:, None] * dgauss
 
     def reset_warm_start(self):
         self.warm = None
@@ -143,10 +177,34 @@ def electric_field(prob, g):
 
 def hdot_in(prob, g):
     """Eq. (4) in the form (9): dh_z/dt = -(d_x e_y - d_y e_x), backward
-    differences from edges back to nodes.  Meaningful at in-nodes only."""
+    differences from edges back to nodes (spectral derivatives in the
+    spectral form).  Meaningful at in-nodes only."""
+    if prob.deriv == "spectral":
+        return hdot_in_spectral(prob, g)
     ex, ey = electric_field(prob, g)
     curl_e = (ey - shift(ey, 1, -1)) / prob.dx - (ex - shift(ex, 0, -1)) / prob.dy
     return -curl_e
+
+
+def spectral_derivative(f, D):
+    """F^{-1}[D F(f)] for a derivative symbol D (Sec. 2.2, spectral form)."""
+    return np.fft.ifft2(D * np.fft.fft2(f)).real
+
+
+def sheet_current_nodes(prob, g):
+    """Eq. (2) at the nodes with spectral derivatives: j_x = d_y g, j_y = -d_x g."""
+    return spectral_derivative(g, prob.DY), -spectral_derivative(g, prob.DX)
+
+
+def hdot_in_spectral(prob, g):
+    """Eq. (4) with every field at the nodes (the paper's discretisation):
+    e = rho(|j|) j, the power law at superconducting nodes and rho_out at the
+    others, then dh_z/dt = -(d_x e_y - d_y e_x)."""
+    jx, jy = sheet_current_nodes(prob, g)
+    s = np.sqrt(jx ** 2 + jy ** 2)
+    rho = resistivity(prob, s, prob.jc_node, prob.sc_node)
+    ex, ey = rho * jx, rho * jy
+    return -(spectral_derivative(ey, prob.DX) - spectral_derivative(ex, prob.DY))
 
 
 def apply_multiplier(f, K):
@@ -210,6 +268,6 @@ def observe(prob, g, t):
     equal to (1/2) int (x j_y - y j_x) because g vanishes outside the film)."""
     he = float(prob.field.h(t)[2])
     hz = he + apply_multiplier(g, prob.K2)
-    jx, jy = sheet_current(prob, g)
+    jx, jy = sheet_current_nodes(prob, g) if prob.deriv == "spectral" else sheet_current(prob, g)
     mz = g.sum() * prob.dx * prob.dy
     return hz, (jx, jy), mz
