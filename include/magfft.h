@@ -73,6 +73,14 @@ enum mag_precision {
                     with dim = 3. */
 };
 
+enum mag_deriv_form {
+  MAG_DERIV_STAGGERED = 0, /* films (default): j on cell edges by differences of g
+                              (eq. (2)), e on the edges, (9) by differences back
+                              to the nodes */
+  MAG_DERIV_SPECTRAL = 1   /* films: every field on the nodes, each derivative the
+                              filtered Fourier multiplier of Sec. 2.2 */
+};
+
 enum mag_field_kind {
   MAG_FIELD_RAMP = 0,   /* h_e(t) = rate * t * dir            (Sec. 2.3: h_e = t) */
   MAG_FIELD_SINE = 1,   /* h_e(t) = amp * sin(omega t) * dir  (Sec. 3.2 cube benchmark) */
@@ -194,7 +202,8 @@ int mag_integrate_captured(mag_ctx *ctx, double *state, double t0, double t1, do
 
 /* Observables of a state (post-processing, Sec. 2.1 last formula):
  * 2D: hz (device, nx*ny, nodes) = h_e + F^{-1}[|k|/2 F(g)]; j (device,
- *     2*nx*ny: j_x on x-edges then j_y on y-edges, eq. (2)); m[0..2] (host)
+ *     2*nx*ny: j_x on x-edges then j_y on y-edges, eq. (2); at the nodes in
+ *     the spectral form of mag_set_derivatives); m[0..2] (host)
  *     = (0, 0, sum g dx dy).
  * 3D: hz (device, nx*ny*nz) = z component of h on z-edges; j (device,
  *     3*nx*ny*nz) = curl h on faces; m (host) = (1/2) sum r x j dV.
@@ -212,6 +221,22 @@ int mag_rhs_vjp(mag_ctx *ctx, const double *state, double t, const double *out_b
 
 /* Forget the warm start: the next mag_rhs starts from dh_e/dt. */
 int mag_reset_warm_start(mag_ctx *ctx);
+
+/* Discretisation of the film right-hand side (eqs. (2)-(4) in the form (9)),
+ * films only (MAG_E_ARG for dim = 3 or another mode).
+ * MAG_DERIV_STAGGERED (the default): differences on the staggered grid.
+ * MAG_DERIV_SPECTRAL (Sec. 2.2): all fields live on the nodes and d/dx_a is
+ * the multiplier i k_a exp(-|k|^2 sigma^2 / 2), the Nyquist wavenumber of
+ * axis a set to zero.  j = (d_y g, -d_x g); e = rho(|j|) j, the power law (3)
+ * at nodes whose four cells are superconducting (jc the mean of the four
+ * cells) and rho_out at every other node; dh_z/dt = -(d_x e_y - d_y e_x) at
+ * the film nodes.  sigma < 0 selects the width of Sec. 2.2, sqrt(dx^2 + dy^2),
+ * for the grid in force at each call.  The update (12) stays unfiltered in
+ * both forms.  mag_observe then returns j at the nodes (j_x, then j_y, each
+ * nx*ny), and mag_rhs_vjp returns MAG_E_STATE (it covers the staggered form).
+ * May be called before or after mag_set_grid; the spectral form holds two
+ * more double arrays of nx*ny on the device.  Drops the warm start. */
+int mag_set_derivatives(mag_ctx *ctx, int mode, double sigma);
 
 /* on = 0: every right-hand side starts the free-space iteration from dh_e/dt
  * (no warm start), which makes f a function of (state, t) alone -- needed

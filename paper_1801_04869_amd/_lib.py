@@ -35,6 +35,7 @@ SIGNATURES = {
     "mag_rhs_vjp": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "mag_reset_warm_start": (c_int, [c_void_p]),
     "mag_set_warm_start": (c_int, [c_void_p, c_int]),
+    "mag_set_derivatives": (c_int, [c_void_p, c_int, c_double]),
     "mag_step_fixed": (c_int, [c_void_p, c_void_p, c_double, c_double]),
     "mag_step_vjp": (c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p]),
     "mag_observe_vjp": (c_int, [c_void_p, c_void_p, c_void_p]),

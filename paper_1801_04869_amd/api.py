@@ -14,6 +14,7 @@ OK, NOT_CONVERGED, STEP_UNDERFLOW = 0, 1, 2
 E_ARG, E_STATE, E_HIP, E_NOMEM, E_NUMERIC = -1, -2, -3, -4, -5
 FP64, MIXED, MIXED_FINAL64 = 0, 1, 2
 RAMP, SINE, ROTATE = 0, 1, 2
+STAGGERED, SPECTRAL = 0, 1
 
 
 class MagError(RuntimeError):
@@ -165,6 +166,11 @@ class Context:
 
     def set_warm_start(self, on=True):
         self._check(self._L.mag_set_warm_start(self._h, 1 if on else 0))
+
+    def set_derivatives(self, mode, sigma=-1.0):
+        """Film discretisation: STAGGERED differences or the SPECTRAL form of
+        Sec. 2.2 (sigma < 0: the width sqrt(dx^2 + dy^2))."""
+        self._check(self._L.mag_set_derivatives(self._h, int(mode), float(sigma)))
 
     def step_fixed(self, state, t, dt):
         """One step of exactly dt without error control (state advances in place)."""

@@ -88,7 +88,8 @@ static hipEvent_t pool_get(mag_ctx *c) {
 static const char *kNames[K_COUNT] = {
     "film_stencil", "film_rows_fwd_h", "film_cols", "film_rows_inv_g", "film_rows_fwd_g", "film_rows_inv_upd",
     "bulk_curl_box", "bulk_efield_box", "bulk_hdot_in", "bulk_x_fwd", "bulk_y_fwd", "bulk_z_phi",
-    "bulk_y_inv", "bulk_x_inv", "finalize", "misc", "rk", "vjp", "film_final64"};
+    "bulk_y_inv", "bulk_x_inv", "finalize", "misc", "rk", "vjp", "film_final64",
+    "film_spectral"};
 
 void prof_begin(mag_ctx *c, int kid, ProfRec *r) {
   r->a = r->b = nullptr;
@@ -520,13 +521,13 @@ static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (
 static void free_all(mag_ctx *c) {
   void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
                   c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_w,
-                  c->d_tw64, c->d_it64, c->d_w64};
+                  c->d_tw64, c->d_it64, c->d_w64, c->d_pm};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_mat = c->d_flags = nullptr;
   c->d_jc = c->d_H = c->d_G = c->d_S = c->d_box = c->d_tw = c->d_w = c->d_tw64 = nullptr;
   c->d_it64 = nullptr;
-  c->d_w64 = nullptr;
+  c->d_w64 = c->d_pm = nullptr;
   c->d_jc64 = c->d_part = c->d_sym = c->d_rk = c->d_red = nullptr;
   c->d_it = nullptr;
   c->nred = 0;
@@ -815,6 +816,23 @@ int mag_reset_warm_start(mag_ctx *c) {
   CHECK_CTX(c);
   c->warm_valid = false;
   c->last_iters = 1;
+  return MAG_OK;
+}
+
+int mag_set_derivatives(mag_ctx *c, int mode, double sigma) {
+  CHECK_CTX(c);
+  if (c->dim != 2) return set_error(c, MAG_E_ARG, "the spectral form is a film option");
+  if (mode != MAG_DERIV_STAGGERED && mode != MAG_DERIV_SPECTRAL)
+    return set_error(c, MAG_E_ARG, "mode must be MAG_DERIV_STAGGERED or MAG_DERIV_SPECTRAL");
+  if (!std::isfinite(sigma)) return set_error(c, MAG_E_ARG, "sigma must be finite");
+  ++c->gen;   // a captured step graph bakes the set-up in
+  MAG_HIP(c, hipStreamSynchronize(c->stream));
+  if (mode == MAG_DERIV_SPECTRAL && c->grid_set && !c->d_pm)
+    MAG_HIP(c, hipMalloc(&c->d_pm, 2 * c->nnode * sizeof(double)));
+  c->deriv = mode;
+  c->dsigma = sigma;
+  c->warm_valid = false;
+  c->fsal_valid = false;
   return MAG_OK;
 }
 

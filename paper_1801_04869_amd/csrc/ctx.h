@@ -74,6 +74,7 @@ enum KernelId {
   K_RK,
   K_VJP,
   K_FILM_FINAL64,
+  K_FILM_SPECTRAL,
   K_COUNT
 };
 
@@ -136,6 +137,9 @@ struct mag_ctx {
   void *d_tw64 = nullptr;         // MAG_MIXED_FINAL64: the same tables in double
   mag::IterState *d_it64 = nullptr;   // MAG_MIXED_FINAL64: gate of the final evaluation
   double *d_w64 = nullptr;        // MAG_MIXED_FINAL64: w1 = K1 1_out in double
+  int deriv = 0;                  // film derivatives: 0 staggered differences, 1 filtered spectral
+  double dsigma = -1;             // spectral form: Gaussian width sigma (< 0: sqrt(dx^2 + dy^2))
+  double *d_pm = nullptr;         // spectral form: two node arrays (j, then e and its derivatives), double
   long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
   double *d_sym = nullptr;        // per-axis symbol tables (double)
   long long sym_off[8] = {0};

@@ -105,12 +105,16 @@ constexpr int kStencilNpt = 4;
 constexpr int kStencilThreads = 1024;
 
 // FP32: two blocks of 16 waves per CU need at most 64 registers per lane.
-template <typename T>
+// SPECTRAL: the inside values come from the spectral derivatives of e
+// already formed (dxey = d_x e_y, dyex = d_y e_x at the nodes) instead of the
+// staggered stencil; the free space and the partial sums are the same.
+template <typename T, bool SPECTRAL = false>
 __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) == 4 ? 8 : 4) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
                                                     T *__restrict__ H, FilmGeom G, FilmLaw law,
                                                     const IterState *__restrict__ it, int warm,
-                                                    double *__restrict__ part) {
+                                                    double *__restrict__ part, const double *__restrict__ dxey,
+                                                    const double *__restrict__ dyex) {
   __shared__ double red[kStencilThreads / 64];
   // a step that has already reached its end time launches nothing useful
   if (it->done) return;
@@ -137,7 +141,10 @@ __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) ==
     if (i >= n) break;
     const int p = (int)(i % G.nx), q = (int)(i / G.nx);
     T h;
-    if (fl[k] & 1) {
+    if (SPECTRAL && (fl[k] & 1)) {
+      h = (T)(-(dxey[i] - dyex[i]));
+      H[i] = h;
+    } else if (fl[k] & 1) {
       const T exq = film_edge_e<T>(g, mat, jc, G, law, p, q, 0);
       const T exm = film_edge_e<T>(g, mat, jc, G, law, p, q - 1, 0);
       const T eyp = film_edge_e<T>(g, mat, jc, G, law, p, q, 1);
@@ -784,6 +791,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // Final double evaluation:
 // MODE 6: write gdot = value - C (double), C = (sum of pp.in) / #out; with
 //         pp.out, sums of |gdot| over free space.
+// Spectral derivatives:
+// MODE 7: write -value (double).
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -864,6 +873,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           X[ro + p] = val[e];
           if (out) acc += (double)val[e];
           acc2 += fabs((double)val[e]);
+        } else if constexpr (MODE == 7) {
+          xd[ro + p] = -(double)val[e];
         } else if constexpr (MODE == 6) {
           const double gd = (double)val[e] - cmean;
           xd[ro + p] = gd;
@@ -874,7 +885,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       }
     }
   }
-  if constexpr (MODE != 2) {
+  if constexpr (MODE != 2 && MODE != 7) {
     if (MODE != 6 || pp.out) {   // uniform over the block
       const double sblk = block_total<RS::THREADS>(acc, red);
       if (threadIdx.x == 0) pp.out[blk] = sblk;
@@ -991,6 +1002,117 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
 #pragma unroll
     for (int rho = 0; rho < RMAX; ++rho) base[j + rho * TT] = v[rho];
   }
+}
+
+// Column pass of a spectral derivative (Sec. 2.2): forward y transform,
+// the symbol i k_a exp(-|k|^2 sigma^2 / 2) / N of axis a (0: x, 1: y),
+// inverse y transform.  kxs, kys: signed wavenumbers with the Nyquist value
+// of each axis set to 0 (an odd symbol has no real value there); k2x, k2y
+// the full squares for the filter; gs = sigma^2 / 2.  The symbol is odd and
+// imaginary, i.e. Hermitian, so the packed kx = 0 / kx = M pencil is split
+// by the same identity as in film_cols with complex multipliers:
+//   W[k] = (m0 + mM)/2 Zh[k] + (m0 - mM)/2 conj Zh[-k].
+template <typename T, int NY>
+__global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
+    film_cols_deriv(cx<T> *__restrict__ S, int kx, const double *__restrict__ k2x, const double *__restrict__ k2y,
+                    const double *__restrict__ kxs, const double *__restrict__ kys, double inv_n, int axis,
+                    double gs, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
+  using CS = FilmColShape<NY, T>;
+  using PL = typename CS::PL;
+  constexpr int TT = CS::TT, P = CS::P, RMAX = PL::RMAX, PITCH = CS::PITCH;
+  __shared__ __align__(16) T lds[CS::LDS_T];
+  const int pcol = threadIdx.x / TT, j = threadIdx.x % TT;
+  TwPre<PL, T, (sizeof(T) > 4)> twp;
+  tw_preload<NY, PL>(twp, j, tw);
+  const int col = blockIdx.x * P + pcol;
+  const bool active = col < kx - 1;
+  const bool pair_block = blockIdx.x == 0;
+  const bool packed = pair_block && pcol == 0;
+  cx<T> *base = S + (long long)(active ? col : 0) * NY;
+  cx<T> *base_m = S + (long long)(kx - 1) * NY;
+  cx<T> v[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int y = j + rho * TT;
+    if (packed) v[rho] = {base[y].x, base_m[y].x};
+    else v[rho] = active ? base[y] : cx<T>{(T)0, (T)0};
+  }
+  T ky2[RMAX], kya[RMAX];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    ky2[rho] = (T)k2y[j + rho * TT];
+    kya[rho] = (T)kys[j + rho * TT];
+  }
+  const T kxx = (T)k2x[active ? col : 0], kxm = (T)k2x[kx - 1];
+  const T kxa = (T)kxs[active ? col : 0], kxam = (T)kxs[kx - 1];
+  if (it->done) return;
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
+  auto lidx = [](int i) { return lds_pad<T>(i); };
+  pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, twp);
+  const T tgs = (T)gs, tn = (T)inv_n;
+  // the real factor s of the symbol i s
+  auto sym = [&](T kk2, T ka) -> T { return ka * exp(-tgs * kk2) * tn; };
+  if (pair_block) {
+    lds_barrier();   // the transform's last LDS reads are done
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) xch[lidx(j + rho * TT)] = v[rho];
+    lds_barrier();
+  }
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const int k = j + rho * TT;
+    const T s0 = sym(kxx + ky2[rho], axis == 0 ? kxa : kya[rho]);
+    if (packed) {
+      const cx<T> zm = conj(xch[lidx((NY - k) & (NY - 1))]);
+      const T sm = sym(kxm + ky2[rho], axis == 0 ? kxam : kya[rho]);
+      const T hp = (T)0.5 * (s0 + sm), hm = (T)0.5 * (s0 - sm);
+      // i (hp Zh[k] + hm conj Zh[-k])
+      const cx<T> u = {hp * v[rho].x + hm * zm.x, hp * v[rho].y + hm * zm.y};
+      v[rho] = {-u.y, u.x};
+    } else {
+      v[rho] = {-s0 * v[rho].y, s0 * v[rho].x};
+    }
+  }
+  pencil_fft_cx<NY, +1, PL>(v, j, xch, lidx, twp);
+  if (packed) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      base[j + rho * TT] = {v[rho].x, (T)0};
+      base_m[j + rho * TT] = {v[rho].y, (T)0};
+    }
+  } else if (active) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) base[j + rho * TT] = v[rho];
+  }
+}
+
+// e = rho(|j|) j at the nodes (the spectral form): the power law at nodes
+// whose four cells are superconducting, jc the mean of the four cells
+// (sum in the order (p,q), (p-1,q), (p,q-1), (p-1,q-1)); rho_out at every
+// other node.  ex_jx / ey_jy hold j_x / j_y on entry and e_x / e_y on exit.
+template <typename T>
+__global__ void __launch_bounds__(256) film_node_e(double *__restrict__ ex_jx, double *__restrict__ ey_jy,
+                                                   const uint8_t *__restrict__ mat, const T *__restrict__ jc,
+                                                   FilmGeom G, FilmLaw law, const IterState *__restrict__ it) {
+  if (it->done) return;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = (long long)G.nx * G.ny;
+  if (i >= n) return;
+  const int p = (int)(i % G.nx), q = (int)(i / G.nx);
+  const long long r0 = (long long)q * G.nx, rm = (long long)wrap(q - 1, G.ny) * G.nx;
+  const int pm = wrap(p - 1, G.nx);
+  const long long c[4] = {r0 + p, r0 + pm, rm + p, rm + pm};
+  bool sc = true;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) sc = sc && mat[c[a]] == 1;
+  const T jt = (T)ex_jx[i], ot = (T)ey_jy[i];
+  T rho = (T)law.rho_out;
+  if (sc) {
+    const T jcn = law.has_jc ? (T)0.25 * (jc[c[0]] + jc[c[1]] + jc[c[2]] + jc[c[3]]) : (T)law.jc0;
+    rho = film_rho(sqrt(jt * jt + ot * ot), jcn, (T)law.e0, (T)law.nm1, (T)law.lmax);
+  }
+  ex_jx[i] = (double)(rho * jt);
+  ey_jy[i] = (double)(rho * ot);
 }
 
 template <typename T>
@@ -1269,6 +1391,7 @@ struct FilmPtrs {
   cx<T> *S;
   const cx<T> *twM, *twY, *twN;
   const double *k2x, *k2y;
+  const double *kxs, *kys;   // signed wavenumbers, Nyquist set to 0 (spectral derivatives)
   T *w1, *w2;   // K1 1_out and K2 1_out (w2: NaN on film nodes)
   T *w1f;       // K1 1_out with NaN on film nodes
 };
@@ -1289,6 +1412,8 @@ static FilmPtrs<T> fptrs(mag_ctx *c) {
   f.twN = tw + c->tw_off[3];
   f.k2x = c->d_sym + c->sym_off[0];
   f.k2y = c->d_sym + c->sym_off[1];
+  f.kxs = c->d_sym + c->sym_off[2];
+  f.kys = c->d_sym + c->sym_off[3];
   f.w1 = reinterpret_cast<T *>(final64 ? c->d_w64 : c->d_w);
   f.w2 = (f.w1 && !final64) ? f.w1 + c->nnode : nullptr;
   f.w1f = (f.w1 && !final64) ? f.w1 + 2 * c->nnode : nullptr;
@@ -1411,6 +1536,35 @@ static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)
   return MAG_OK;
 }
 
+// Column pass of the spectral derivative along axis (0: x, 1: y).
+template <typename T>
+static int film_col_deriv(mag_ctx *c, int axis, int kid) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  // the Gaussian width of Sec. 2.2, by default sqrt(dx^2 + dy^2)
+  const double sig = c->dsigma < 0 ? std::hypot(c->d[0], c->d[1]) : c->dsigma;
+  ProfLaunch ps(c, kid);
+  FILM_SWITCH_N(G.ny, {
+    using CS = FilmColShape<NN, T>;
+    const int nblk = (G.kx - 1 + CS::P - 1) / CS::P;
+    MAG_TIMED_LAUNCH(ps, (film_cols_deriv<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x,
+                     f.k2y, f.kxs, f.kys, 1.0 / (double)c->nnode, axis, 0.5 * sig * sig, f.twY,
+                     (const IterState *)c->d_it);
+  });
+  return MAG_OK;
+}
+
+// dst = d/dx_axis of the double array src (spectral form), or its negative
+// (neg): row R2C, derivative column pass, row C2R.
+template <typename T>
+static int film_spectral_derivative(mag_ctx *c, const double *src, int axis, double *dst, bool neg, int kid) {
+  int rc;
+  if ((rc = film_fwd<T, 2>(c, nullptr, src, 0.0, parts(nullptr, 0, nullptr), kid))) return rc;
+  if ((rc = film_col_deriv<T>(c, axis, kid))) return rc;
+  if (neg) return film_inv<T, 7>(c, nullptr, dst, 0.0, parts(nullptr, 0, nullptr), kid);
+  return film_inv<T, 2>(c, nullptr, dst, 0.0, parts(nullptr, 0, nullptr), kid);
+}
+
 // One inner iteration i (evaluation i of (11), then the update (12)), four
 // passes over the spectrum:
 //   (i = 0: rows_fwd  H: shift A^0 from the stencil sums, R2C of H - dh_e,
@@ -1494,6 +1648,44 @@ static FilmLaw film_law(const mag_ctx *c) {
   return law;
 }
 
+// The film values of dh_z/dt (eq. (9)), the free-space start and the partial
+// sums of H - dh_e: the staggered stencil, or in the spectral form (Sec.
+// 2.2) j = (d_y g, -d_x g) at the nodes, e = rho(|j|) j there, and
+// -(d_x e_y - d_y e_x), all with the filtered Fourier derivatives.
+template <typename T>
+static int film_stencil_pass(mag_ctx *c, const double *state, int warm) {
+  FilmPtrs<T> f = fptrs<T>(c);
+  const FilmGeom G = fgeom(c);
+  const FilmLaw law = film_law(c);
+  const int nbs = film_stencil_blocks(c);
+  if (c->deriv == 0) {
+    ProfLaunch ps(c, K_FILM_STENCIL);
+    MAG_TIMED_LAUNCH(ps, (film_stencil<T, false>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
+                     c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm,
+                     film_regions<T>(c).X, (const double *)nullptr, (const double *)nullptr);
+    return MAG_OK;
+  }
+  if (!c->d_pm) return set_error(c, MAG_E_STATE, "spectral derivatives without their buffers");
+  const long long n = c->nnode;
+  double *a = c->d_pm, *b = c->d_pm + n;
+  int rc;
+  if ((rc = film_spectral_derivative<T>(c, state, 1, a, false, K_FILM_SPECTRAL))) return rc;   // j_x = d_y g
+  if ((rc = film_spectral_derivative<T>(c, state, 0, b, true, K_FILM_SPECTRAL))) return rc;    // j_y = -d_x g
+  {
+    ProfScope ps(c, K_FILM_SPECTRAL);
+    hipLaunchKernelGGL((film_node_e<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, a, b,
+                       c->d_mat, reinterpret_cast<const T *>(c->d_jc), G, law, (const IterState *)c->d_it);
+  }
+  if ((rc = film_spectral_derivative<T>(c, b, 0, b, false, K_FILM_SPECTRAL))) return rc;   // d_x e_y
+  if ((rc = film_spectral_derivative<T>(c, a, 1, a, false, K_FILM_SPECTRAL))) return rc;   // d_y e_x
+  ProfLaunch ps(c, K_FILM_STENCIL);
+  MAG_TIMED_LAUNCH(ps, (film_stencil<T, true>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
+                   c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm, film_regions<T>(c).X,
+                   (const double *)b, (const double *)a);
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
 // The right-hand side with a fixed inner count, enqueued only: the iteration
 // state (dh_e/dt included) has been set on the device by the caller, the
 // free-space iterate holds the warm start, and the last evaluation writes
@@ -1501,16 +1693,8 @@ static FilmLaw film_law(const mag_ctx *c) {
 // can be captured in a graph.
 template <typename T>
 static int film_rhs_enqueue_t(mag_ctx *c, const double *state, double *out) {
-  FilmPtrs<T> f = fptrs<T>(c);
-  const FilmGeom G = fgeom(c);
-  const FilmLaw law = film_law(c);
   const int nbs = film_stencil_blocks(c);
-  {
-    ProfLaunch ps(c, K_FILM_STENCIL);
-    MAG_TIMED_LAUNCH(ps, (film_stencil<T>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
-                     c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, 1,
-                     film_regions<T>(c).X);
-  }
+  if (int rc = film_stencil_pass<T>(c, state, 1)) return rc;
   for (int i = 0; i < c->fixed_iters; ++i) {
     c->cur_iter = i;
     if (int rc = film_iteration<T>(c, 0.0, i, nbs, out)) return rc;
@@ -1543,13 +1727,8 @@ static int film_rhs_t(mag_ctx *c, const double *state, double t, double *out, in
   const FilmLaw law = film_law(c);
   const long long n = c->nnode;
   const int nbs = film_stencil_blocks(c);
-  {
-    ProfLaunch ps(c, K_FILM_STENCIL);
-    MAG_TIMED_LAUNCH(ps, (film_stencil<T>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat, c->d_flags,
-                       reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, c->warm_valid ? 1 : 0,
-                       film_regions<T>(c).X);
-  }
-  int rc = MAG_OK;
+  int rc = film_stencil_pass<T>(c, state, c->warm_valid ? 1 : 0);
+  if (rc) return rc;
   MAG_HIP(c, hipGetLastError());
   const int kmax = c->fixed_iters > 0 ? c->fixed_iters : c->max_inner;
   int issued = 0;
@@ -1628,8 +1807,14 @@ static int film_observe_t(mag_ctx *c, const double *state, double t, double *hz,
     if ((rc = film_col<T>(c, 1))) return rc;
     if ((rc = film_inv<T, 2>(c, nullptr, hz, he[2], parts(nullptr, 0, nullptr), K_MISC))) return rc;
   }
+  if (j && c->deriv == 1) {
+    // j_x = d_y g and j_y = -d_x g at the nodes (spectral form)
+    if ((rc = film_spectral_derivative<T>(c, state, 1, j, false, K_MISC))) return rc;
+    if ((rc = film_spectral_derivative<T>(c, state, 0, j + n, true, K_MISC))) return rc;
+  }
   ProfScope ps(c, K_MISC);
-  if (j) hipLaunchKernelGGL(film_current, dim3(nb), dim3(256), 0, c->stream, state, j, G.nx, G.ny, G.idx, G.idy);
+  if (j && c->deriv == 0)
+    hipLaunchKernelGGL(film_current, dim3(nb), dim3(256), 0, c->stream, state, j, G.nx, G.ny, G.idx, G.idy);
   // m_z = sum g dx dy: fixed-order two-level sum
   hipLaunchKernelGGL(sum_blocks, dim3(nb), dim3(256), 0, c->stream, state, n, c->d_part);
   std::vector<double> parts(nb);
@@ -1766,6 +1951,7 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
 
 int film_rhs_vjp(mag_ctx *c, const double *state, double, const double *out_bar, double *state_bar,
                  double *jc_bar) {
+  if (c->deriv != 0) return set_error(c, MAG_E_STATE, "the VJP covers the staggered differences only");
   return c->prec == MAG_FP64 ? film_rhs_vjp_t<double>(c, state, out_bar, state_bar, jc_bar)
                              : film_rhs_vjp_t<float>(c, state, out_bar, state_bar, jc_bar);
 }
@@ -1787,6 +1973,7 @@ int film_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_w, 3 * n * ts));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
   MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
+  if (c->deriv == 1) MAG_HIP(c, hipMalloc(&c->d_pm, 2 * n * sizeof(double)));
   if (c->prec == MAG_MIXED_FINAL64) {
     MAG_HIP(c, hipMalloc(&c->d_it64, sizeof(IterState)));
     MAG_HIP(c, hipMemsetAsync(c->d_it64, 0, sizeof(IterState), c->stream));
@@ -1805,6 +1992,14 @@ int film_alloc(mag_ctx *c) {
     const double k = 2.0 * M_PI * (double)(m < (ny + 1) / 2 ? m : m - ny) / (ny * c->d[1]);
     sym.push_back(k * k);
   }
+  // signed wavenumbers of the spectral derivatives, the Nyquist value of
+  // each axis set to 0: x over the half spectrum, then y
+  c->sym_off[2] = (long long)sym.size();
+  for (int m = 0; m < c->kx; ++m)
+    sym.push_back(m == nx / 2 ? 0.0 : 2.0 * M_PI * (double)m / (nx * c->d[0]));
+  c->sym_off[3] = (long long)sym.size();
+  for (int m = 0; m < ny; ++m)
+    sym.push_back(m == ny / 2 ? 0.0 : 2.0 * M_PI * (double)(m < (ny + 1) / 2 ? m : m - ny) / (ny * c->d[1]));
   MAG_HIP(c, hipMalloc(&c->d_sym, sym.size() * sizeof(double)));
   MAG_HIP(c, hipMemcpy(c->d_sym, sym.data(), sym.size() * sizeof(double), hipMemcpyHostToDevice));
   return MAG_OK;

@@ -41,12 +41,14 @@ def bulk_case(nx, ny, nz, L=(2.0, 2.0, 2.0), half=(1.0, 1.0, 1.0), n=25.0, jc_s=
                 field=field)
 
 
-def make_gpu(case, precision=0, lam=0.7, tol=None, max_inner=100, fixed=0):
+def make_gpu(case, precision=0, lam=0.7, tol=None, max_inner=100, fixed=0, deriv="staggered"):
     import torch
     from paper_1801_04869_amd import api
     c = api.Context(case["dim"], precision)
     nx, ny, nz = case["n"]
     c.set_grid(nx, ny, nz, *case["L"])
+    if deriv == "spectral":
+        c.set_derivatives(api.SPECTRAL)
     c.set_domain(torch.from_numpy(np.ascontiguousarray(case["mat"])).cuda())
     jc = None if case["jc"] is None else torch.from_numpy(np.ascontiguousarray(case["jc"])).cuda()
     c.set_params(jc, 1.0, case["nexp"], 1.0, case["rho_out"])
@@ -56,7 +58,7 @@ def make_gpu(case, precision=0, lam=0.7, tol=None, max_inner=100, fixed=0):
     return c
 
 
-def make_oracle(case, lam=0.7, tol=None, max_inner=100, fixed=0):
+def make_oracle(case, lam=0.7, tol=None, max_inner=100, fixed=0, deriv="staggered"):
     from oracle import bulk, film
     from oracle.field import AppliedField
     f = case["field"]
@@ -66,7 +68,7 @@ def make_oracle(case, lam=0.7, tol=None, max_inner=100, fixed=0):
         return film.FilmProblem(nx, ny, case["L"][0], case["L"][1], case["mat"], jc_cell=case["jc"],
                                 n=case["nexp"], rho_out=case["rho_out"], lam=lam,
                                 tol=2e-4 if tol is None else tol, max_inner=max_inner, fixed_iters=fixed,
-                                field=fld)
+                                field=fld, deriv=deriv)
     return bulk.BulkProblem(nx, ny, nz, *case["L"], case["mat"], jc_cell=case["jc"], n=case["nexp"],
                             rho_out=case["rho_out"], tol=1e-4 if tol is None else tol, max_inner=max_inner,
                             fixed_iters=fixed, field=fld)

@@ -64,11 +64,13 @@ def P(a):
     return ctypes.c_void_p(a.ctypes.data)
 
 
-def setup(L, case, prec, fixed=0, max_inner=100, tol=None):
+def setup(L, case, prec, fixed=0, max_inner=100, tol=None, deriv="staggered"):
     h = ctypes.c_void_p()
     assert L.mag_create(ctypes.byref(h), case["dim"], prec, None) == 0
     nx, ny, nz = case["n"]
     assert L.mag_set_grid(h, nx, ny, nz, *case["L"]) == 0, L.mag_last_error(h)
+    if deriv == "spectral":
+        assert L.mag_set_derivatives(h, 1, -1.0) == 0, L.mag_last_error(h)
     mat = Dev(np.ascontiguousarray(case["mat"], dtype=np.uint8))
     assert L.mag_set_domain(h, P(mat)) == 0, L.mag_last_error(h)
     jc = None if case["jc"] is None else Dev(np.ascontiguousarray(case["jc"]))
@@ -163,10 +165,22 @@ def main(path, which):
                   # column passes of 1024 and 2048 rows: two column groups per block
                   ("film", film_case(16, 1024, L=(0.25, 2.0), kind="offrect", jc_s=0.2), 1, 2),
                   ("film", film_case(16, 2048, L=(0.25, 2.0), kind="offrect", jc_s=0.2), 0, 1)]
-    for name, case, prec, fixed in cases:
-        h, keep = setup(L, case, prec, fixed=fixed)
+    if which in ("spectral", "all"):
+        # the spectral form of Sec. 2.2 (fields on the nodes, filtered Fourier
+        # derivatives), every precision, fixed counts and the stop test
+        sp = "spectral"
+        cases += [("spectral", film_case(32, 16, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 2, sp),
+                  ("spectral", film_case(16, 32, L=(1.0, 2.0), kind="ring", rho_out=20.0), 1, 1, sp),
+                  ("spectral", film_case(64, 32, L=(2.0, 1.0), kind="ring", jc_s=0.2, rho_out=20.0), 2, 3, sp),
+                  ("spectral", film_case(32, 32, L=(1.0, 1.0), kind="disk"), 0, 0, sp),
+                  ("spectral", film_case(32, 32, L=(1.0, 1.0), kind="disk"), 2, 0, sp),
+                  ("spectral", film_case(16, 1024, L=(0.25, 2.0), kind="offrect", jc_s=0.2), 1, 2, sp)]
+    for entry in cases:
+        name, case, prec, fixed = entry[:4]
+        deriv = entry[4] if len(entry) > 4 else "staggered"
+        h, keep = setup(L, case, prec, fixed=fixed, deriv=deriv)
         rc, it, out = run_rhs(L, h, case["state"], 0.2)
-        prob = make_oracle(case, fixed=fixed)
+        prob = make_oracle(case, fixed=fixed, deriv=deriv)
         mod = film if case["dim"] == 2 else bulk
         ref, rit, rst = mod.rhs(prob, case["state"], 0.2)
         err = rel_l2(out, ref)
@@ -177,7 +191,15 @@ def main(path, which):
         fails += not ok
         print("%-10s n=%s prec=%d fixed=%d rc=%d it=%d rel-L2=%.3e %s" % (name, case["n"], prec, fixed, rc, it, err,
                                                                          "ok" if ok else "FAIL"), flush=True)
-        if case["dim"] == 2:
+        if deriv == "spectral":
+            # the VJP covers the staggered form only
+            s_ = Dev(np.ascontiguousarray(case["state"]))
+            d_ = Dev(like=case["state"])
+            rc = L.mag_rhs_vjp(h, P(s_), 0.2, P(d_), P(d_), None)
+            okv = rc == -2
+            fails += not okv
+            print("   vjp refused rc=%d %s" % (rc, "ok" if okv else "FAIL"), flush=True)
+        elif case["dim"] == 2:
             # vector-Jacobian product against the oracle's transpose
             from oracle import adjoint
             ybar_h = np.random.default_rng(7).standard_normal(case["state"].shape)
@@ -202,6 +224,12 @@ def main(path, which):
         jj = Dev(np.zeros(case["dim"] * nn))
         rc = L.mag_observe(h, P(s), 0.3, P(hz), P(jj), m)
         print("   observe rc=%d m=%s" % (rc, list(m)), flush=True)
+        if case["dim"] == 2:
+            rhz, (rjx, rjy), rmz = film.observe(prob, case["state"], 0.3)
+            eo = max(rel_l2(hz.numpy(), rhz.ravel()), rel_l2(jj.numpy(), np.concatenate([rjx.ravel(), rjy.ravel()])))
+            oko = rc == 0 and eo < (1e-10 if prec == 0 else 1e-5)
+            fails += not oko
+            print("   observe vs oracle rel-L2=%.3e %s" % (eo, "ok" if oko else "FAIL"), flush=True)
         if case["dim"] == 2:
             # the allocation-free moment against mag_observe's
             md = Dev(np.full(3, np.nan))

@@ -42,6 +42,7 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert L.mag_last_error(None) == b"null context"
     assert L.mag_set_grid(None, 16, 16, 16, 1.0, 1.0, 1.0) == -1
     assert L.mag_rhs(None, None, 0.0, None, None) == -1
+    assert L.mag_set_derivatives(None, 1, -1.0) == -1
     assert L.mag_prof_kernel_name(0) is not None
     assert L.mag_prof_kernel_name(10 ** 6) is None
     L.mag_destroy(None)
@@ -58,6 +59,6 @@ def test_python_constants_match_the_header():
              "E_ARG": "MAG_E_ARG", "E_STATE": "MAG_E_STATE", "E_HIP": "MAG_E_HIP", "E_NOMEM": "MAG_E_NOMEM",
              "E_NUMERIC": "MAG_E_NUMERIC", "FP64": "MAG_FP64", "MIXED": "MAG_MIXED",
              "MIXED_FINAL64": "MAG_MIXED_FINAL64", "RAMP": "MAG_FIELD_RAMP", "SINE": "MAG_FIELD_SINE",
-             "ROTATE": "MAG_FIELD_ROTATE"}
+             "ROTATE": "MAG_FIELD_ROTATE", "STAGGERED": "MAG_DERIV_STAGGERED", "SPECTRAL": "MAG_DERIV_SPECTRAL"}
     for py, c in pairs.items():
         assert getattr(api, py) == enum[c], (py, c)
