@@ -146,12 +146,14 @@ def recorded_traffic(kernel, prec):
     return None
 
 
-def make_ctx(prec, wl, mat, jc, fixed=0, lam=0.7, max_inner=200):
+def make_ctx(prec, wl, mat, jc, fixed=0, lam=0.7, max_inner=200, deriv="staggered"):
     import torch
     from paper_1801_04869_amd import api
     nx, ny = wl["n"]
     ctx = api.Context(2, {"mixed": api.MIXED, "fp64": api.FP64, "final64": api.MIXED_FINAL64}[prec])
     ctx.set_grid(nx, ny, 1, *wl["L"])
+    if deriv == "spectral":
+        ctx.set_derivatives(api.SPECTRAL)
     ctx.set_domain(torch.from_numpy(mat).cuda())
     ctx.set_params(torch.from_numpy(jc).cuda(), 1.0, wl["nexp"], 1.0, wl["rho_out"])
     ctx.set_solver(lam, 2e-4, max_inner, fixed)
@@ -313,7 +315,40 @@ def observe_time(prec, wl, mat, jc, g, t, reps=20):
     return round(1e3 * dt / reps, 4)
 
 
-def converged_window(prec, wl, mat, jc, lam, warm_attempts, attempts):
+def spectral_run(prec, wl, mat, jc, g, steps, warmup, t, fixed, lam):
+    """The fixed-count loop of run_gpu with the spectral form of Sec. 2.2
+    (fields on the nodes, filtered Fourier derivatives): RHS/s without
+    instrumentation, then the per-kernel breakdown from a loop with events
+    on every dispatch."""
+    import torch
+    ctx = make_ctx(prec, wl, mat, jc, fixed, lam=lam, deriv="spectral")
+    state = torch.from_numpy(g).cuda()
+    out = torch.empty_like(state)
+
+    def loop(n):
+        for _ in range(n):
+            ctx.reset_warm_start()
+            st, it = ctx.rhs(state, t, out)
+            assert st == 0, ctx.last_error()
+
+    loop(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.prof_enable(True)
+    loop(steps)
+    prof = ctx.prof_read()
+    ctx.prof_enable(False)
+    ctx.close()
+    per_rhs = {k: dict(launches_per_rhs=round(c / steps, 2), us_per_rhs=round(1e3 * ms / steps, 2),
+                       avg_us=round(1e3 * ms / c, 2)) for k, (c, ms) in prof.items()}
+    return dict(value=round(steps / dt, 3), unit="RHS evals/s", ms_per_step=round(1e3 * dt / steps, 4),
+                kernels=per_rhs)
+
+
+def converged_window(prec, wl, mat, jc, lam, warm_attempts, attempts, deriv="staggered"):
     """Right-hand sides of an adaptive BS23 run with the stop test: from the
     virgin state g = 0 at t = 0, `warm_attempts` step attempts (untimed) bring
     the film to a state reached by integration; the next `attempts` attempts
@@ -322,7 +357,7 @@ def converged_window(prec, wl, mat, jc, lam, warm_attempts, attempts):
     the library, stage sums and step control included in the time) and the
     mean inner iteration count."""
     import torch
-    ctx = make_ctx(prec, wl, mat, jc, 0, lam=lam, max_inner=200)
+    ctx = make_ctx(prec, wl, mat, jc, 0, lam=lam, max_inner=200, deriv=deriv)
     y = torch.zeros((wl["n"][1], wl["n"][0]), dtype=torch.float64, device="cuda")
     ts, hs = 0.0, 1e-7
     for _ in range(warm_attempts):
@@ -565,6 +600,24 @@ def main():
             for mask in masks for p in ("mixed", "final64") if "%s-%s" % (mask, p) in conv}
         line["film_2048_fixed%d" % a.iters]["kernels_fp64"] = kernel_table(f64["prof"], n, kx, ny, "fp64", a.iters,
                                                                            n_out)
+    # the paper's own discretisation (spectral form) on the headline mask
+    sp_lines = {}
+    for prec in precs:
+        r = spectral_run(prec, wl, mat, jc, g, a.steps, a.warmup, a.t, a.iters, LAMBDA_2048[a.mask])
+        r["over_staggered"] = round(r["value"] / res[(a.mask, prec)]["value"], 3)
+        sp_lines[prec] = r
+        print("[bench] film-2048-%s spectral %s fixed %d: %.1f RHS/s" % (a.mask, prec, a.iters, r["value"]),
+              file=sys.stderr, flush=True)
+    sp_conv = {}
+    for prec in precs[:1] if a.quick else ("mixed", "fp64"):
+        c = converged_window(prec, wl, mat, jc, LAMBDA_2048[a.mask], a.warmup, a.window, deriv="spectral")
+        sp_conv[prec] = c
+        print("[bench] film-2048-%s spectral %s converged: %.1f RHS/s, I = %.2f" %
+              (a.mask, prec, c["value"], c["mean_inner_iters"]), file=sys.stderr, flush=True)
+    line["film_2048_spectral"] = dict(
+        workload=film_workload + "; spectral form of Sec. 2.2 (j, e and dh_z/dt on the nodes from filtered "
+                                 "Fourier derivatives, sigma = sqrt(dx^2 + dy^2))",
+        fixed=sp_lines, converged=sp_conv)
     line["adjoint_forward_ratio_film"] = round(m["vjp_ms"] / m["ms_per_step"], 3)
     line["bs23_step_ms"] = round(m["step_ms"], 4)
     line["bs23_step_over_3_rhs"] = round(m["step_ms"] * m["value_stream"] / 3e3, 3)

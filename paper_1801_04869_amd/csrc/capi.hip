@@ -521,13 +521,14 @@ static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (
 static void free_all(mag_ctx *c) {
   void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
                   c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_w,
-                  c->d_tw64, c->d_it64, c->d_w64, c->d_pm};
+                  c->d_tw64, c->d_it64, c->d_w64, c->d_S2, c->d_jcn};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_mat = c->d_flags = nullptr;
   c->d_jc = c->d_H = c->d_G = c->d_S = c->d_box = c->d_tw = c->d_w = c->d_tw64 = nullptr;
   c->d_it64 = nullptr;
-  c->d_w64 = c->d_pm = nullptr;
+  c->d_w64 = nullptr;
+  c->d_S2 = c->d_jcn = nullptr;
   c->d_jc64 = c->d_part = c->d_sym = c->d_rk = c->d_red = nullptr;
   c->d_it = nullptr;
   c->nred = 0;
@@ -827,8 +828,11 @@ int mag_set_derivatives(mag_ctx *c, int mode, double sigma) {
   if (!std::isfinite(sigma)) return set_error(c, MAG_E_ARG, "sigma must be finite");
   ++c->gen;   // a captured step graph bakes the set-up in
   MAG_HIP(c, hipStreamSynchronize(c->stream));
-  if (mode == MAG_DERIV_SPECTRAL && c->grid_set && !c->d_pm)
-    MAG_HIP(c, hipMalloc(&c->d_pm, 2 * c->nnode * sizeof(double)));
+  if (mode == MAG_DERIV_SPECTRAL && c->grid_set && !c->d_S2) {
+    const size_t ts = c->prec == MAG_FP64 ? 8 : 4;
+    MAG_HIP(c, hipMalloc(&c->d_S2, c->nspec * 2 * ts));
+    MAG_HIP(c, hipMalloc(&c->d_jcn, c->nnode * ts));
+  }
   c->deriv = mode;
   c->dsigma = sigma;
   c->warm_valid = false;

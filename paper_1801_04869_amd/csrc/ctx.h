@@ -139,7 +139,9 @@ struct mag_ctx {
   double *d_w64 = nullptr;        // MAG_MIXED_FINAL64: w1 = K1 1_out in double
   int deriv = 0;                  // film derivatives: 0 staggered differences, 1 filtered spectral
   double dsigma = -1;             // spectral form: Gaussian width sigma (< 0: sqrt(dx^2 + dy^2))
-  double *d_pm = nullptr;         // spectral form: two node arrays (j, then e and its derivatives), double
+  void *d_S2 = nullptr;           // spectral form: second half spectrum (j_y, then e_y), precision type
+  void *d_jcn = nullptr;          // spectral form: per-node jc, NaN off superconducting nodes (precision type)
+  long long jcn_gen = -1;         // set-up generation d_jcn was computed for
   long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
   double *d_sym = nullptr;        // per-axis symbol tables (double)
   long long sym_off[8] = {0};

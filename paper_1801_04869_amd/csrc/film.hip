@@ -105,16 +105,14 @@ constexpr int kStencilNpt = 4;
 constexpr int kStencilThreads = 1024;
 
 // FP32: two blocks of 16 waves per CU need at most 64 registers per lane.
-// SPECTRAL: the inside values come from the spectral derivatives of e
-// already formed (dxey = d_x e_y, dyex = d_y e_x at the nodes) instead of the
-// staggered stencil; the free space and the partial sums are the same.
+// SPECTRAL: the film values of H have been written by the spectral passes
+// and are only read here; the free space and the partial sums are the same.
 template <typename T, bool SPECTRAL = false>
 __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) == 4 ? 8 : 4) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
                                                     T *__restrict__ H, FilmGeom G, FilmLaw law,
                                                     const IterState *__restrict__ it, int warm,
-                                                    double *__restrict__ part, const double *__restrict__ dxey,
-                                                    const double *__restrict__ dyex) {
+                                                    double *__restrict__ part) {
   __shared__ double red[kStencilThreads / 64];
   // a step that has already reached its end time launches nothing useful
   if (it->done) return;
@@ -133,7 +131,7 @@ __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) ==
     const long long i = i0 + (long long)k * kStencilThreads;
     const long long ic = i < n ? i : 0;
     fl[k] = flags[ic];
-    hw[k] = warm ? H[ic] : (T)0;
+    hw[k] = (warm || SPECTRAL) ? H[ic] : (T)0;
   }
 #pragma unroll 1
   for (int k = 0; k < kStencilNpt; ++k) {
@@ -142,8 +140,7 @@ __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) ==
     const int p = (int)(i % G.nx), q = (int)(i / G.nx);
     T h;
     if (SPECTRAL && (fl[k] & 1)) {
-      h = (T)(-(dxey[i] - dyex[i]));
-      H[i] = h;
+      h = hw[k];
     } else if (fl[k] & 1) {
       const T exq = film_edge_e<T>(g, mat, jc, G, law, p, q, 0);
       const T exm = film_edge_e<T>(g, mat, jc, G, law, p, q - 1, 0);
@@ -791,8 +788,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // Final double evaluation:
 // MODE 6: write gdot = value - C (double), C = (sum of pp.in) / #out; with
 //         pp.out, sums of |gdot| over free space.
-// Spectral derivatives:
-// MODE 7: write -value (double).
+// Spectral form:
+// MODE 7: write the value into X at film nodes (flag bit 0), nothing else.
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -874,7 +871,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           if (out) acc += (double)val[e];
           acc2 += fabs((double)val[e]);
         } else if constexpr (MODE == 7) {
-          xd[ro + p] = -(double)val[e];
+          if (!out) X[ro + p] = val[e];
         } else if constexpr (MODE == 6) {
           const double gd = (double)val[e] - cmean;
           xd[ro + p] = gd;
@@ -1004,38 +1001,47 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   }
 }
 
-// Column pass of a spectral derivative (Sec. 2.2): forward y transform,
-// the symbol i k_a exp(-|k|^2 sigma^2 / 2) / N of axis a (0: x, 1: y),
-// inverse y transform.  kxs, kys: signed wavenumbers with the Nyquist value
-// of each axis set to 0 (an odd symbol has no real value there); k2x, k2y
-// the full squares for the filter; gs = sigma^2 / 2.  The symbol is odd and
-// imaginary, i.e. Hermitian, so the packed kx = 0 / kx = M pencil is split
-// by the same identity as in film_cols with complex multipliers:
+// Column passes of the spectral form (Sec. 2.2).  A derivative d/dx_a is
+// the symbol i s_a, s_a = k_a exp(-|k|^2 sigma^2 / 2) / N (N = nx ny, the
+// normalisation of the two transforms), with k_a the signed wavenumber of
+// axis a and its Nyquist value set to 0 (an odd symbol has no real value
+// there): kxs, kys; k2x, k2y the full squares for the filter; gs =
+// sigma^2 / 2.  The symbols are Hermitian, so the packed kx = 0 / kx = M
+// pencil is split by the identity of film_cols with complex multipliers,
 //   W[k] = (m0 + mM)/2 Zh[k] + (m0 - mM)/2 conj Zh[-k].
-template <typename T, int NY>
+// OP 0 (gradient): from the spectrum of g in S, the spectra of j_x = d_y g
+//      (to S) and j_y = -d_x g (to S2), eq. (2) at the nodes.
+// OP 1 (curl): from the spectra of e_x (S) and e_y (S2), the spectrum of
+//      dh_z/dt = d_y e_x - d_x e_y (to S), eq. (9).
+template <typename T, int NY, int OP>
 __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
-    film_cols_deriv(cx<T> *__restrict__ S, int kx, const double *__restrict__ k2x, const double *__restrict__ k2y,
-                    const double *__restrict__ kxs, const double *__restrict__ kys, double inv_n, int axis,
-                    double gs, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
+    film_cols_spec(cx<T> *__restrict__ S, cx<T> *__restrict__ S2, int kx, const double *__restrict__ k2x,
+                   const double *__restrict__ k2y, const double *__restrict__ kxs, const double *__restrict__ kys,
+                   double inv_n, double gs, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
   using CS = FilmColShape<NY, T>;
   using PL = typename CS::PL;
   constexpr int TT = CS::TT, P = CS::P, RMAX = PL::RMAX, PITCH = CS::PITCH;
   __shared__ __align__(16) T lds[CS::LDS_T];
   const int pcol = threadIdx.x / TT, j = threadIdx.x % TT;
-  TwPre<PL, T, (sizeof(T) > 4)> twp;
+  // OP 1 holds two transformed columns: twiddle powers formed per stage
+  TwPre<PL, T, (sizeof(T) > 4 || OP == 1)> twp;
   tw_preload<NY, PL>(twp, j, tw);
   const int col = blockIdx.x * P + pcol;
   const bool active = col < kx - 1;
-  const bool pair_block = blockIdx.x == 0;
+  const bool pair_block = blockIdx.x == 0;   // uniform over the block
   const bool packed = pair_block && pcol == 0;
-  cx<T> *base = S + (long long)(active ? col : 0) * NY;
-  cx<T> *base_m = S + (long long)(kx - 1) * NY;
-  cx<T> v[RMAX];
+  const long long co = (long long)(active ? col : 0) * NY, cm = (long long)(kx - 1) * NY;
+  // OP 0: v = the spectrum of g; OP 1: v = e_x, u = e_y
+  cx<T> v[RMAX], u[RMAX];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
     const int y = j + rho * TT;
-    if (packed) v[rho] = {base[y].x, base_m[y].x};
-    else v[rho] = active ? base[y] : cx<T>{(T)0, (T)0};
+    if (packed) v[rho] = {S[co + y].x, S[cm + y].x};
+    else v[rho] = active ? S[co + y] : cx<T>{(T)0, (T)0};
+    if constexpr (OP == 1) {
+      if (packed) u[rho] = {S2[co + y].x, S2[cm + y].x};
+      else u[rho] = active ? S2[co + y] : cx<T>{(T)0, (T)0};
+    }
   }
   T ky2[RMAX], kya[RMAX];
 #pragma unroll
@@ -1049,52 +1055,81 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
   auto lidx = [](int i) { return lds_pad<T>(i); };
   pencil_fft_cx<NY, -1, PL>(v, j, xch, lidx, twp);
-  const T tgs = (T)gs, tn = (T)inv_n;
-  // the real factor s of the symbol i s
-  auto sym = [&](T kk2, T ka) -> T { return ka * exp(-tgs * kk2) * tn; };
-  if (pair_block) {
-    lds_barrier();   // the transform's last LDS reads are done
+  // (each transform starts with a barrier: a column has at least two stages)
+  if constexpr (OP == 1) pencil_fft_cx<NY, -1, PL>(u, j, xch, lidx, twp);
+  // the packed pencil reads the mirrored entries conj Zh[-k] of a transform
+  // from the LDS (block 0 only; the next transform starts with a barrier)
+  auto mirror_to_lds = [&](const cx<T> *w) {
+    if (pair_block) {
+      lds_barrier();
 #pragma unroll
-    for (int rho = 0; rho < RMAX; ++rho) xch[lidx(j + rho * TT)] = v[rho];
-    lds_barrier();
-  }
+      for (int rho = 0; rho < RMAX; ++rho) xch[lidx(j + rho * TT)] = w[rho];
+      lds_barrier();
+    }
+  };
+  const T tgs = (T)gs, tn = (T)inv_n;
+  // i (hp Z + hm conj Z[-k]) with hp = (s0 + sM) / 2, hm = (s0 - sM) / 2; i s0 Z off the packed pencil
+  auto apply = [&](const cx<T> &z, int k, T s0, T sm) -> cx<T> {
+    if (packed) {
+      const cx<T> zm = conj(xch[lidx((NY - k) & (NY - 1))]);
+      const T hp = (T)0.5 * (s0 + sm), hm = (T)0.5 * (s0 - sm);
+      return {-(hp * z.y + hm * zm.y), hp * z.x + hm * zm.x};
+    }
+    return {-s0 * z.y, s0 * z.x};
+  };
+  // the filter at (kx, ky) and, on the packed pencil, at (M, ky)
+  auto filt = [&](int rho, T &f0, T &fm) {
+    f0 = exp(-tgs * (kxx + ky2[rho])) * tn;
+    fm = packed ? exp(-tgs * (kxm + ky2[rho])) * tn : (T)0;
+  };
+  mirror_to_lds(v);
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
     const int k = j + rho * TT;
-    const T s0 = sym(kxx + ky2[rho], axis == 0 ? kxa : kya[rho]);
-    if (packed) {
-      const cx<T> zm = conj(xch[lidx((NY - k) & (NY - 1))]);
-      const T sm = sym(kxm + ky2[rho], axis == 0 ? kxam : kya[rho]);
-      const T hp = (T)0.5 * (s0 + sm), hm = (T)0.5 * (s0 - sm);
-      // i (hp Zh[k] + hm conj Zh[-k])
-      const cx<T> u = {hp * v[rho].x + hm * zm.x, hp * v[rho].y + hm * zm.y};
-      v[rho] = {-u.y, u.x};
-    } else {
-      v[rho] = {-s0 * v[rho].y, s0 * v[rho].x};
+    T f0, fm;
+    filt(rho, f0, fm);
+    if constexpr (OP == 0) {
+      u[rho] = apply(v[rho], k, -kxa * f0, -kxam * fm);       // j_y = -d_x g
+    }
+    v[rho] = apply(v[rho], k, kya[rho] * f0, kya[rho] * fm);  // j_x = d_y g, or d_y e_x
+  }
+  if constexpr (OP == 1) {
+    mirror_to_lds(u);
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      T f0, fm;
+      filt(rho, f0, fm);
+      const cx<T> b = apply(u[rho], j + rho * TT, kxa * f0, kxam * fm);   // d_x e_y
+      v[rho] = {v[rho].x - b.x, v[rho].y - b.y};
     }
   }
   pencil_fft_cx<NY, +1, PL>(v, j, xch, lidx, twp);
-  if (packed) {
+  auto store = [&](cx<T> *__restrict__ D, const cx<T> *w) {
+    if (packed) {
 #pragma unroll
-    for (int rho = 0; rho < RMAX; ++rho) {
-      base[j + rho * TT] = {v[rho].x, (T)0};
-      base_m[j + rho * TT] = {v[rho].y, (T)0};
+      for (int rho = 0; rho < RMAX; ++rho) {
+        D[co + j + rho * TT] = {w[rho].x, (T)0};
+        D[cm + j + rho * TT] = {w[rho].y, (T)0};
+      }
+    } else if (active) {
+#pragma unroll
+      for (int rho = 0; rho < RMAX; ++rho) D[co + j + rho * TT] = w[rho];
     }
-  } else if (active) {
-#pragma unroll
-    for (int rho = 0; rho < RMAX; ++rho) base[j + rho * TT] = v[rho];
+  };
+  store(S, v);
+  if constexpr (OP == 0) {
+    pencil_fft_cx<NY, +1, PL>(u, j, xch, lidx, twp);
+    store(S2, u);
   }
 }
 
-// e = rho(|j|) j at the nodes (the spectral form): the power law at nodes
-// whose four cells are superconducting, jc the mean of the four cells
-// (sum in the order (p,q), (p-1,q), (p,q-1), (p-1,q-1)); rho_out at every
-// other node.  ex_jx / ey_jy hold j_x / j_y on entry and e_x / e_y on exit.
+// Per-node critical current of the spectral form: the mean of the four cells
+// around node (p, q) (summed in the order (p,q), (p-1,q), (p,q-1),
+// (p-1,q-1)) where all four are superconducting, NaN at every other node
+// (rho_out applies there).
 template <typename T>
-__global__ void __launch_bounds__(256) film_node_e(double *__restrict__ ex_jx, double *__restrict__ ey_jy,
-                                                   const uint8_t *__restrict__ mat, const T *__restrict__ jc,
-                                                   FilmGeom G, FilmLaw law, const IterState *__restrict__ it) {
-  if (it->done) return;
+__global__ void __launch_bounds__(256) film_node_jc(const uint8_t *__restrict__ mat, const T *__restrict__ jc,
+                                                    T *__restrict__ jcn, FilmGeom G, FilmLaw law) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long n = (long long)G.nx * G.ny;
   if (i >= n) return;
@@ -1105,14 +1140,117 @@ __global__ void __launch_bounds__(256) film_node_e(double *__restrict__ ex_jx, d
   bool sc = true;
 #pragma unroll
   for (int a = 0; a < 4; ++a) sc = sc && mat[c[a]] == 1;
-  const T jt = (T)ex_jx[i], ot = (T)ey_jy[i];
-  T rho = (T)law.rho_out;
-  if (sc) {
-    const T jcn = law.has_jc ? (T)0.25 * (jc[c[0]] + jc[c[1]] + jc[c[2]] + jc[c[3]]) : (T)law.jc0;
-    rho = film_rho(sqrt(jt * jt + ot * ot), jcn, (T)law.e0, (T)law.nm1, (T)law.lmax);
+  const T v = law.has_jc ? (T)0.25 * (jc[c[0]] + jc[c[1]] + jc[c[2]] + jc[c[3]]) : (T)law.jc0;
+  jcn[i] = sc ? v : (T)NAN;
+}
+
+// Row pass of the spectral form between its two column passes: C2R of the
+// spectra of j_x (S) and j_y (S2) along x, e = rho(|j|) j at each node (the
+// power law (3) where jcn is a number, rho_out where it is NaN), R2C of e_x
+// (to S) and e_y (to S2).  Same tiles, twiddles and packing as
+// film_rows_fused; the two components pass through the LDS one after the
+// other.
+template <typename T, int M>
+__global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
+    MAG_WAVES_PER_EU(FilmRowShape<M, T>::WAVES_EU)
+    film_rows_node_e(cx<T> *__restrict__ S, cx<T> *__restrict__ S2, const T *__restrict__ jcn,
+                     const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN, FilmGeom G, FilmLaw law,
+                     const IterState *__restrict__ it) {
+  using RS = FilmRowShape<M, T>;
+  using PL = typename RS::PL;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ __align__(16) T lds[RS::LDS_T];
+  const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
+  const int q0 = blk * P;
+  const int q = q0 + pr;
+  const long long ro = (long long)(q < G.ny ? q : 0) * G.nx;
+  cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
+  TileRegs<T, M, P, RS::THREADS> t1, t2;
+  tile_fetch(t1, S, G.ny, q0);
+  tile_fetch(t2, S2, G.ny, q0);
+  RowTw<T, M, RS::THREADS> rtw;
+  row_tw_fetch(rtw, twM, twN);
+  if (it->done) return;
+  T jn[RMAX][2];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const long long o = ro + 2 * (j + rho * TT);
+    jn[rho][0] = jcn[o];
+    jn[rho][1] = jcn[o + 1];
   }
-  ex_jx[i] = (double)(rho * jt);
-  ey_jy[i] = (double)(rho * ot);
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
+  auto lidx = [](int i) { return lds_pad<T>(i); };
+  // C2R of the tile: Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]);
+  // its inverse transform holds the values of nodes 2m, 2m+1
+  auto c2r = [&](cx<T> *vv) {
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const int k = j + rho * TT;
+      const cx<T> a = tile[k * SP + pr];
+      const cx<T> b = tile[(M - k) * SP + pr];
+      const cx<T> sum = {a.x + b.x, a.y - b.y};
+      const cx<T> dif = {a.x - b.x, a.y + b.y};
+      const cx<T> wd = cmulc(dif, twN[k]);
+      vv[rho] = {sum.x - wd.y, sum.y + wd.x};
+    }
+    if constexpr (PL::S == 1) __syncthreads();   // single-stage FFTs do not fence the tile
+    pencil_fft_cx<M, +1, PL>(vv, j, xch, lidx, twM);
+  };
+  // R2C of the node values in vv into the tile, then to D
+  auto r2c_store = [&](cx<T> *vv, cx<T> *__restrict__ D) {
+    pencil_fft_cx<M, -1, PL>(vv, j, xch, lidx, twM);
+    __syncthreads();
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) xch[j + rho * TT] = vv[rho];
+    __syncthreads();
+    cx<T> xk[RMAX];
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const int k = j + rho * TT;
+      const int km = (M - k) & (M - 1);
+      const cx<T> zk = vv[rho];
+      const cx<T> zm = conj(xch[km]);
+      const cx<T> sum = zk + zm, dif = zk - zm;
+      const cx<T> wd = cmul(twN[k], dif);
+      xk[rho] = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
+    }
+    const cx<T> xm = {vv[0].x - vv[0].y, (T)0};
+    __syncthreads();
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
+    if (j == 0) tile[M * SP + pr] = xm;
+    __syncthreads();
+    tile_store<T, M, P, SP, RS::THREADS>(tile, D, G.ny, q0);
+  };
+  tile_put<T, M, P, SP, RS::THREADS>(tile, t1);
+  row_tw_put(rtw, twM, twN);
+  __syncthreads();
+  cx<T> jx[RMAX], jy[RMAX];
+  c2r(jx);
+  __syncthreads();   // the transform's last LDS reads are done
+  tile_put<T, M, P, SP, RS::THREADS>(tile, t2);
+  __syncthreads();
+  c2r(jy);
+  const T e0 = (T)law.e0, nm1 = (T)law.nm1, lmax = (T)law.lmax, rout = (T)law.rho_out;
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const T ax[2] = {jx[rho].x, jx[rho].y}, ay[2] = {jy[rho].x, jy[rho].y};
+    T ex[2], ey[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const T jcv = jn[rho][e];
+      const T r = isnan(jcv) ? rout : film_rho(sqrt(ax[e] * ax[e] + ay[e] * ay[e]), jcv, e0, nm1, lmax);
+      ex[e] = r * ax[e];
+      ey[e] = r * ay[e];
+    }
+    jx[rho] = {ex[0], ex[1]};
+    jy[rho] = {ey[0], ey[1]};
+  }
+  __syncthreads();   // the second C2R's last LDS reads are done
+  r2c_store(jx, S);
+  __syncthreads();   // the tile has been read out
+  r2c_store(jy, S2);
 }
 
 template <typename T>
@@ -1478,7 +1616,8 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, in
 }
 
 template <typename T, int MODE>
-static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid, IterState *its = nullptr) {
+static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid, IterState *its = nullptr,
+                    const cx<T> *src = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfLaunch ps(c, kid);
@@ -1486,7 +1625,7 @@ static int film_inv(mag_ctx *c, T *X, double *xd, double hde, Parts pp, int kid,
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     MAG_TIMED_LAUNCH(ps, (film_rows_inv<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
-                       c->d_flags, f.S, f.twM, f.twN, G, hde, c->lambda, pp, its ? its : c->d_it);
+                       c->d_flags, src ? src : f.S, f.twM, f.twN, G, hde, c->lambda, pp, its ? its : c->d_it);
   });
   return MAG_OK;
 }
@@ -1536,9 +1675,9 @@ static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)
   return MAG_OK;
 }
 
-// Column pass of the spectral derivative along axis (0: x, 1: y).
-template <typename T>
-static int film_col_deriv(mag_ctx *c, int axis, int kid) {
+// Column pass of the spectral form (OP 0: gradient of g, OP 1: curl of e).
+template <typename T, int OP>
+static int film_col_spec(mag_ctx *c, int kid) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   // the Gaussian width of Sec. 2.2, by default sqrt(dx^2 + dy^2)
@@ -1547,22 +1686,53 @@ static int film_col_deriv(mag_ctx *c, int axis, int kid) {
   FILM_SWITCH_N(G.ny, {
     using CS = FilmColShape<NN, T>;
     const int nblk = (G.kx - 1 + CS::P - 1) / CS::P;
-    MAG_TIMED_LAUNCH(ps, (film_cols_deriv<T, NN>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S, G.kx, f.k2x,
-                     f.k2y, f.kxs, f.kys, 1.0 / (double)c->nnode, axis, 0.5 * sig * sig, f.twY,
-                     (const IterState *)c->d_it);
+    MAG_TIMED_LAUNCH(ps, (film_cols_spec<T, NN, OP>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S,
+                     reinterpret_cast<cx<T> *>(c->d_S2), G.kx, f.k2x, f.k2y, f.kxs, f.kys, 1.0 / (double)c->nnode,
+                     0.5 * sig * sig, f.twY, (const IterState *)c->d_it);
   });
   return MAG_OK;
 }
 
-// dst = d/dx_axis of the double array src (spectral form), or its negative
-// (neg): row R2C, derivative column pass, row C2R.
+// The spectrum of g in S becomes the spectra of j_x (S) and j_y (S2).
 template <typename T>
-static int film_spectral_derivative(mag_ctx *c, const double *src, int axis, double *dst, bool neg, int kid) {
+static int film_spectral_current(mag_ctx *c, const double *state, int kid) {
   int rc;
-  if ((rc = film_fwd<T, 2>(c, nullptr, src, 0.0, parts(nullptr, 0, nullptr), kid))) return rc;
-  if ((rc = film_col_deriv<T>(c, axis, kid))) return rc;
-  if (neg) return film_inv<T, 7>(c, nullptr, dst, 0.0, parts(nullptr, 0, nullptr), kid);
-  return film_inv<T, 2>(c, nullptr, dst, 0.0, parts(nullptr, 0, nullptr), kid);
+  if ((rc = film_fwd<T, 2>(c, nullptr, state, 0.0, parts(nullptr, 0, nullptr), kid))) return rc;
+  return film_col_spec<T, 0>(c, kid);
+}
+
+static FilmLaw film_law(const mag_ctx *c);
+
+// The film values of dh_z/dt in the spectral form, written into H at the
+// film nodes: j from g, e = rho(|j|) j at the nodes, d_y e_x - d_x e_y.
+template <typename T>
+static int film_spectral_film_values(mag_ctx *c, const double *state) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  const FilmLaw law = film_law(c);
+  if (!c->d_S2 || !c->d_jcn) return set_error(c, MAG_E_STATE, "spectral form without its buffers");
+  if (c->jcn_gen != c->gen) {
+    // the per-node jc follows the material and the jc map
+    ProfScope ps(c, K_FILM_SPECTRAL);
+    hipLaunchKernelGGL((film_node_jc<T>), dim3((unsigned)((c->nnode + 255) / 256)), dim3(256), 0, c->stream,
+                       c->d_mat, reinterpret_cast<const T *>(c->d_jc), reinterpret_cast<T *>(c->d_jcn), G, law);
+    MAG_HIP(c, hipGetLastError());
+    c->jcn_gen = c->gen;
+  }
+  int rc;
+  if ((rc = film_spectral_current<T>(c, state, K_FILM_SPECTRAL))) return rc;
+  {
+    ProfLaunch ps(c, K_FILM_SPECTRAL);
+    FILM_SWITCH_M(G.nx / 2, {
+      using RS = FilmRowShape<MM, T>;
+      const int nblk = (G.ny + RS::P - 1) / RS::P;
+      MAG_TIMED_LAUNCH(ps, (film_rows_node_e<T, MM>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, f.S,
+                       reinterpret_cast<cx<T> *>(c->d_S2), reinterpret_cast<const T *>(c->d_jcn), f.twM, f.twN, G,
+                       law, (const IterState *)c->d_it);
+    });
+  }
+  if ((rc = film_col_spec<T, 1>(c, K_FILM_SPECTRAL))) return rc;
+  return film_inv<T, 7>(c, f.H, nullptr, 0.0, parts(nullptr, 0, nullptr), K_FILM_SPECTRAL);
 }
 
 // One inner iteration i (evaluation i of (11), then the update (12)), four
@@ -1650,8 +1820,8 @@ static FilmLaw film_law(const mag_ctx *c) {
 
 // The film values of dh_z/dt (eq. (9)), the free-space start and the partial
 // sums of H - dh_e: the staggered stencil, or in the spectral form (Sec.
-// 2.2) j = (d_y g, -d_x g) at the nodes, e = rho(|j|) j there, and
-// -(d_x e_y - d_y e_x), all with the filtered Fourier derivatives.
+// 2.2) the film values from the spectral passes, then the same stencil
+// kernel for the free space and the sums.
 template <typename T>
 static int film_stencil_pass(mag_ctx *c, const double *state, int warm) {
   FilmPtrs<T> f = fptrs<T>(c);
@@ -1662,26 +1832,13 @@ static int film_stencil_pass(mag_ctx *c, const double *state, int warm) {
     ProfLaunch ps(c, K_FILM_STENCIL);
     MAG_TIMED_LAUNCH(ps, (film_stencil<T, false>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
                      c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm,
-                     film_regions<T>(c).X, (const double *)nullptr, (const double *)nullptr);
+                     film_regions<T>(c).X);
     return MAG_OK;
   }
-  if (!c->d_pm) return set_error(c, MAG_E_STATE, "spectral derivatives without their buffers");
-  const long long n = c->nnode;
-  double *a = c->d_pm, *b = c->d_pm + n;
-  int rc;
-  if ((rc = film_spectral_derivative<T>(c, state, 1, a, false, K_FILM_SPECTRAL))) return rc;   // j_x = d_y g
-  if ((rc = film_spectral_derivative<T>(c, state, 0, b, true, K_FILM_SPECTRAL))) return rc;    // j_y = -d_x g
-  {
-    ProfScope ps(c, K_FILM_SPECTRAL);
-    hipLaunchKernelGGL((film_node_e<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, a, b,
-                       c->d_mat, reinterpret_cast<const T *>(c->d_jc), G, law, (const IterState *)c->d_it);
-  }
-  if ((rc = film_spectral_derivative<T>(c, b, 0, b, false, K_FILM_SPECTRAL))) return rc;   // d_x e_y
-  if ((rc = film_spectral_derivative<T>(c, a, 1, a, false, K_FILM_SPECTRAL))) return rc;   // d_y e_x
+  if (int rc = film_spectral_film_values<T>(c, state)) return rc;
   ProfLaunch ps(c, K_FILM_STENCIL);
   MAG_TIMED_LAUNCH(ps, (film_stencil<T, true>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
-                   c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm, film_regions<T>(c).X,
-                   (const double *)b, (const double *)a);
+                   c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm, film_regions<T>(c).X);
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
 }
@@ -1809,8 +1966,11 @@ static int film_observe_t(mag_ctx *c, const double *state, double t, double *hz,
   }
   if (j && c->deriv == 1) {
     // j_x = d_y g and j_y = -d_x g at the nodes (spectral form)
-    if ((rc = film_spectral_derivative<T>(c, state, 1, j, false, K_MISC))) return rc;
-    if ((rc = film_spectral_derivative<T>(c, state, 0, j + n, true, K_MISC))) return rc;
+    if ((rc = film_spectral_current<T>(c, state, K_MISC))) return rc;
+    if ((rc = film_inv<T, 2>(c, nullptr, j, 0.0, parts(nullptr, 0, nullptr), K_MISC))) return rc;
+    if ((rc = film_inv<T, 2>(c, nullptr, j + n, 0.0, parts(nullptr, 0, nullptr), K_MISC, nullptr,
+                             reinterpret_cast<const cx<T> *>(c->d_S2))))
+      return rc;
   }
   ProfScope ps(c, K_MISC);
   if (j && c->deriv == 0)
@@ -1973,7 +2133,10 @@ int film_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_w, 3 * n * ts));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
   MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
-  if (c->deriv == 1) MAG_HIP(c, hipMalloc(&c->d_pm, 2 * n * sizeof(double)));
+  if (c->deriv == 1) {
+    MAG_HIP(c, hipMalloc(&c->d_S2, c->nspec * 2 * ts));
+    MAG_HIP(c, hipMalloc(&c->d_jcn, n * ts));
+  }
   if (c->prec == MAG_MIXED_FINAL64) {
     MAG_HIP(c, hipMalloc(&c->d_it64, sizeof(IterState)));
     MAG_HIP(c, hipMemsetAsync(c->d_it64, 0, sizeof(IterState), c->stream));
