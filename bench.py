@@ -348,6 +348,47 @@ def spectral_run(prec, wl, mat, jc, g, steps, warmup, t, fixed, lam):
                 kernels=per_rhs)
 
 
+def hole_film_lines(a):
+    """RHS/s on the film of Sec. 2.3, Fig. 3: fixed count on a Bean-like
+    snapshot and converged right-hand sides of an adaptive window from the
+    virgin state, both film forms, mixed and FP64."""
+    import torch
+    from paper_1801_04869_amd import workloads as W
+    wl = W.workload("film-768x512-hole")
+    nx, ny = wl["n"]
+    Lx, Ly = wl["L"]
+    h = wl["hole"]
+    mat = W.film_rect_hole(nx, ny, Lx, Ly, h["ax"], h["ay"], h["cx"], h["cy"], h["r"])
+    jc = np.ones((ny, nx))
+    g = W.film_snapshot(mat, 2 * Lx / nx, delta=0.15, seed=1806)
+    out = dict(workload="film-768x512-hole: rectangle |x| <= 1.5, |y| <= 1 with the hole (x-0.5)^2 + (y-0.25)^2 "
+                        "<= 0.25 filled by a normal conductor, 768x512 grid on |x| <= 2.25, |y| <= 1.5, n = 50, "
+                        "rho_out = 500, h_e = t, uniform jc, lambda %g; fixed: %d inner iterations on a Bean-like "
+                        "snapshot at t = 0.3; converged: adaptive BS23 window from g = 0" % (wl["lam"], a.iters))
+    for form in ("staggered", "spectral"):
+        for prec in ("mixed", "fp64"):
+            ctx = make_ctx(prec, wl, mat, jc, a.iters, lam=wl["lam"], deriv=form)
+            state = torch.from_numpy(g).cuda()
+            o = torch.empty_like(state)
+            for _ in range(a.warmup):
+                ctx.reset_warm_start()
+                ctx.rhs(state, 0.3, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                ctx.reset_warm_start()
+                st, _ = ctx.rhs(state, 0.3, o)
+                assert st == 0, ctx.last_error()
+            torch.cuda.synchronize()
+            fixed = a.steps / (time.perf_counter() - t0)
+            ctx.close()
+            conv = converged_window(prec, wl, mat, jc, wl["lam"], a.warmup, a.window, deriv=form)
+            out["%s-%s" % (form, prec)] = dict(fixed_rhs_per_s=round(fixed, 1), converged=conv)
+            print("[bench] film-768x512-hole %s %s: fixed %d %.1f RHS/s, converged %.1f RHS/s (I = %.2f)" %
+                  (form, prec, a.iters, fixed, conv["value"], conv["mean_inner_iters"]), file=sys.stderr, flush=True)
+    return out
+
+
 def converged_window(prec, wl, mat, jc, lam, warm_attempts, attempts, deriv="staggered"):
     """Right-hand sides of an adaptive BS23 run with the stop test: from the
     virgin state g = 0 at t = 0, `warm_attempts` step attempts (untimed) bring
@@ -618,6 +659,9 @@ def main():
         workload=film_workload + "; spectral form of Sec. 2.2 (j, e and dh_z/dt on the nodes from filtered "
                                  "Fourier derivatives, sigma = sqrt(dx^2 + dy^2))",
         fixed=sp_lines, converged=sp_conv)
+    # the film with a circular hole of Sec. 2.3, Fig. 3 (768 x 512, radix-12 row transforms)
+    if not a.quick:
+        line["film_768x512_hole"] = hole_film_lines(a)
     line["adjoint_forward_ratio_film"] = round(m["vjp_ms"] / m["ms_per_step"], 3)
     line["bs23_step_ms"] = round(m["step_ms"], 4)
     line["bs23_step_over_3_rhs"] = round(m["step_ms"] * m["value_stream"] / 3e3, 3)

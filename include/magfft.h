@@ -97,8 +97,10 @@ void mag_destroy(mag_ctx *ctx);
 
 /* Uniform grid on D = [-Lx,Lx] x [-Ly,Ly] (x [-Lz,Lz]) with nx x ny (x nz)
  * nodes (Sec. 2.2 and 3.1).  nz must be 1 for dim 2.  Allocates the FFT and
- * iteration workspace.  Errors: MAG_E_ARG (sizes not powers of two in
- * [16, 2048], non-positive lengths), MAG_E_NOMEM; MAG_E_STATE for a 3D grid
+ * iteration workspace.  Sizes: powers of two in [16, 2048]; a film may also
+ * have nx or ny = 3 * 2^k in [48, 768] (the 768 x 512 film of Sec. 2.3,
+ * Fig. 3), transformed with a radix-12 first stage.
+ * Errors: MAG_E_ARG (other sizes, non-positive lengths), MAG_E_NOMEM; MAG_E_STATE for a 3D grid
  * in GPU builds: the 3D path is compiled but disabled there (held off the GPU
  * after an unexplained memory fault); only the CPU emulation build of the
  * sources enables it. */

@@ -517,6 +517,8 @@ using namespace mag;
 extern "C" {
 
 static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+// three times a power of two in [lo, hi]
+static bool pow2x3_in(int n, int lo, int hi) { return n % 3 == 0 && pow2_in(n / 3, (lo + 2) / 3, hi / 3); }
 
 static void free_all(mag_ctx *c) {
   void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
@@ -601,8 +603,12 @@ const char *mag_last_error(const mag_ctx *c) { return c ? c->err.c_str() : "null
 int mag_set_grid(mag_ctx *c, int nx, int ny, int nz, double Lx, double Ly, double Lz) {
   CHECK_CTX(c);
   ++c->gen;   // a captured step graph bakes the set-up in
-  if (!pow2_in(nx, 16, 2048) || !pow2_in(ny, 16, 2048))
+  if (c->dim == 3 && (!pow2_in(nx, 16, 2048) || !pow2_in(ny, 16, 2048)))
     return set_error(c, MAG_E_ARG, "nx, ny must be powers of two in [16, 2048]");
+  if (c->dim == 2 && (!(pow2_in(nx, 16, 2048) || pow2x3_in(nx, 48, 768)) ||
+                      !(pow2_in(ny, 16, 2048) || pow2x3_in(ny, 48, 768))))
+    return set_error(c, MAG_E_ARG,
+                     "film grid: nx, ny powers of two in [16, 2048] or three times one in [48, 768]");
   if (c->dim == 2 && nz != 1) return set_error(c, MAG_E_ARG, "nz must be 1 for a film");
   if (c->dim == 3 && !pow2_in(nz, 16, 2048)) return set_error(c, MAG_E_ARG, "nz must be a power of two in [16, 2048]");
   if (!(Lx > 0) || !(Ly > 0) || (c->dim == 3 && !(Lz > 0))) return set_error(c, MAG_E_ARG, "box half-lengths must be positive");

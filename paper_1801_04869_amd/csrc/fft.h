@@ -1,6 +1,7 @@
 // Device building blocks of the pencil FFTs (gfx950, wave64).
 //
-// A pencil of length N (a power of two, 8..4096) is spread over TT = N / RMAX
+// A pencil of length N (a power of two, 8..4096, or three times a power of
+// two, 12..768, whose first stage is a radix-12 DFT) is spread over TT = N / RMAX
 // threads; thread j holds the RMAX values x[j + rho * TT] in registers.  The
 // transform is a mixed-radix Stockham decimation-in-time: stage s combines
 // sub-transforms of length Ns (product of the earlier radices) with radix R_s.
@@ -8,7 +9,8 @@
 // register pattern above straight from global memory and the last stage
 // leaves X[j + rho * TT] in registers, so a two-stage pencil costs one LDS
 // exchange.  In-register DFTs of size 2..16 are unrolled radix-2 butterflies
-// with compile-time twiddles; inter-stage twiddles come from a table of
+// with compile-time twiddles, size 12 a prime-factor (3 x 4) composition
+// without internal twiddles; inter-stage twiddles come from a table of
 // exp(-2 pi i m / N) built on the host in double precision.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -87,11 +89,54 @@ __device__ __forceinline__ cx<T> rot(cx<T> a) {
   }
 }
 
-// In-register DFT of size R (2, 4, 8 or 16), natural order in and out.
+// In-register DFT of size 3, natural order: A_k = sum_n a_n w^(nk) with
+// w = exp(DIR 2 pi i / 3) = -1/2 + DIR i sin(2 pi / 3).
+template <int DIR, typename T>
+__device__ __forceinline__ void dft3(cx<T>& a0, cx<T>& a1, cx<T>& a2) {
+  const T h = (T)(DIR * 0.86602540378443865);   // DIR sin(2 pi / 3)
+  const cx<T> t = a1 + a2, d = a1 - a2;
+  const cx<T> m = {a0.x - (T)0.5 * t.x, a0.y - (T)0.5 * t.y};
+  const cx<T> id = {-h * d.y, h * d.x};          // DIR i sin(2 pi / 3) (a1 - a2)
+  a0 = a0 + t;
+  a1 = m + id;
+  a2 = m - id;
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T>* v);
+
+// In-register DFT of size 12 by the prime-factor (Good-Thomas) map 12 = 3 x 4:
+// input index n = (4 n1 + 3 n2) mod 12, output index k = (4 k1 + 9 k2) mod 12,
+// so that nk = 4 n1 k1 + 3 n2 k2 (mod 12): three-point DFTs over n1 for each
+// n2, then four-point DFTs over n2 for each k1, with no twiddles between.
+template <int DIR, typename T>
+__device__ __forceinline__ void dft12(cx<T>* v) {
+  cx<T> y[3][4];
+  static_for<0, 4>([&](auto n2I) {
+    constexpr int n2 = decltype(n2I)::value;
+    cx<T> a0 = v[(3 * n2) % 12], a1 = v[(4 + 3 * n2) % 12], a2 = v[(8 + 3 * n2) % 12];
+    dft3<DIR, T>(a0, a1, a2);
+    y[0][n2] = a0;
+    y[1][n2] = a1;
+    y[2][n2] = a2;
+  });
+  static_for<0, 3>([&](auto k1I) {
+    constexpr int k1 = decltype(k1I)::value;
+    dft<4, DIR, T>(y[k1]);
+    static_for<0, 4>([&](auto k2I) {
+      constexpr int k2 = decltype(k2I)::value;
+      v[(4 * k1 + 9 * k2) % 12] = y[k1][k2];
+    });
+  });
+}
+
+// In-register DFT of size R (2, 4, 8, 16 or 12), natural order in and out.
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T>* v) {
   if constexpr (R == 1) {
     return;
+  } else if constexpr (R == 12) {
+    dft12<DIR, T>(v);
   } else {
     static_for<0, ilog2(R)>([&](auto st) {
       constexpr int span = R >> (decltype(st)::value + 1);
@@ -153,7 +198,22 @@ MAG_PLAN(Plan8, 512, 3, 8, 8, 8, 8, 1)
 MAG_PLAN(Plan8, 1024, 4, 8, 8, 8, 8, 2)
 MAG_PLAN(Plan8, 2048, 4, 8, 8, 8, 8, 4)
 MAG_PLAN(Plan8, 4096, 4, 8, 8, 8, 8, 8)
+// three times a power of two: a radix-12 first stage, twelve values per thread
+MAG_PLAN(Plan8, 12, 1, 12, 12, 1, 1, 1)
+MAG_PLAN(Plan8, 24, 2, 12, 12, 2, 1, 1)
+MAG_PLAN(Plan8, 48, 2, 12, 12, 4, 1, 1)
+MAG_PLAN(Plan8, 96, 3, 12, 12, 4, 2, 1)
+MAG_PLAN(Plan8, 192, 3, 12, 12, 4, 4, 1)
+MAG_PLAN(Plan8, 384, 4, 12, 12, 4, 4, 2)
+MAG_PLAN(Plan8, 768, 4, 12, 12, 4, 4, 4)
 #undef MAG_PLAN
+
+// b mod n for b >= 0 (a mask when n is a power of two)
+template <int n>
+__device__ __forceinline__ int mod_len(int b) {
+  if constexpr ((n & (n - 1)) == 0) return b & (n - 1);
+  else return (int)((unsigned)b % (unsigned)n);
+}
 
 template <typename PL, int s>
 constexpr int plan_ns() {
@@ -199,7 +259,7 @@ __device__ __forceinline__ void pencil_fft(cx<T>* v, int j, T* lre, T* lim, LIdx
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = j + u * TT;
-      const int k = b & (Ns - 1);
+      const int k = mod_len<Ns>(b);
       cx<T> a[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) a[r] = v[u + r * U];
@@ -273,7 +333,7 @@ __device__ __forceinline__ void tw_preload(TwPre<PL, T, LOCAL>& t, int j, const 
     constexpr int Ns = plan_ns<PL, s>();
     constexpr int tstep = N / (Ns * R);
 #pragma unroll
-    for (int u = 0; u < U; ++u) t.w[plan_twoff<PL>(s) + u] = tw[((j + u * TT) & (Ns - 1)) * tstep];
+    for (int u = 0; u < U; ++u) t.w[plan_twoff<PL>(s) + u] = tw[mod_len<Ns>(j + u * TT) * tstep];
   });
 }
 
@@ -320,7 +380,7 @@ __device__ __forceinline__ void pencil_fft_cx(cx<T>* v, int j, cx<T>* lds, LIdx 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = j + u * TT;
-      const int k = b & (Ns - 1);
+      const int k = mod_len<Ns>(b);
       cx<T> a[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) a[r] = v[u + r * U];

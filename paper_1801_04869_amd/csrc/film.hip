@@ -25,7 +25,14 @@ namespace mag {
 
 namespace {
 
-__device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
+// Periodic index for -n <= i < 2n (grid lengths are powers of two or three
+// times a power of two); P2: n is a power of two (a mask).
+template <bool P2 = false>
+__device__ __forceinline__ int wrap(int i, int n) {
+  if constexpr (P2) return i & (n - 1);
+  i = i < 0 ? i + n : i;
+  return i >= n ? i - n : i;
+}
 
 // LDS exchange slot of complex element i of a pencil: one padding element
 // after every 128 bytes (16 FP32 or 8 FP64 complex values); the pencil's
@@ -64,25 +71,26 @@ struct FilmLaw {
   int has_jc;
 };
 
-// e on the x-edge (p, q+1/2) or the y-edge (p+1/2, q) (orient 0 / 1).
-template <typename T>
+// e on the x-edge (p, q+1/2) or the y-edge (p+1/2, q) (orient 0 / 1);
+// P2: nx and ny are powers of two.
+template <typename T, bool P2>
 __device__ __forceinline__ T film_edge_e(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                          const T *__restrict__ jc, const FilmGeom &G, const FilmLaw &law,
                                          int p, int q, int orient) {
   const int nx = G.nx, ny = G.ny;
-  auto gv = [&](int pp, int qq) { return g[(long long)wrap(qq, ny) * nx + wrap(pp, nx)]; };
+  auto gv = [&](int pp, int qq) { return g[(long long)wrap<P2>(qq, ny) * nx + wrap<P2>(pp, nx)]; };
   auto jxv = [&](int pp, int qq) { return (gv(pp, qq + 1) - gv(pp, qq)) * G.idy; };
   auto jyv = [&](int pp, int qq) { return -(gv(pp + 1, qq) - gv(pp, qq)) * G.idx; };
   double jo, oth;
-  long long c0 = (long long)wrap(q, ny) * nx + wrap(p, nx), c1;
+  long long c0 = (long long)wrap<P2>(q, ny) * nx + wrap<P2>(p, nx), c1;
   if (orient == 0) {
     jo = jxv(p, q);
     oth = 0.25 * (jyv(p - 1, q) + jyv(p, q) + jyv(p - 1, q + 1) + jyv(p, q + 1));
-    c1 = (long long)wrap(q, ny) * nx + wrap(p - 1, nx);
+    c1 = (long long)wrap<P2>(q, ny) * nx + wrap<P2>(p - 1, nx);
   } else {
     jo = jyv(p, q);
     oth = 0.25 * (jxv(p, q - 1) + jxv(p, q) + jxv(p + 1, q - 1) + jxv(p + 1, q));
-    c1 = (long long)wrap(q - 1, ny) * nx + wrap(p, nx);
+    c1 = (long long)wrap<P2>(q - 1, ny) * nx + wrap<P2>(p, nx);
   }
   const uint8_t m0 = mat[c0], m1 = mat[c1];
   if (m0 == 1 && m1 == 1) {
@@ -104,11 +112,12 @@ __device__ __forceinline__ T film_edge_e(const double *__restrict__ g, const uin
 constexpr int kStencilNpt = 4;
 constexpr int kStencilThreads = 1024;
 
-// FP32: two blocks of 16 waves per CU need at most 64 registers per lane.
+// FP32: two blocks of 16 waves per CU need at most 64 registers per lane
+// (the general periodic wrap of grids of 3 * 2^k nodes needs more: one block).
 // SPECTRAL: the film values of H have been written by the spectral passes
 // and are only read here; the free space and the partial sums are the same.
-template <typename T, bool SPECTRAL = false>
-__global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) == 4 ? 8 : 4) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
+template <typename T, bool SPECTRAL, bool P2>
+__global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) == 4 && (P2 || SPECTRAL) ? 8 : 4) film_stencil(const double *__restrict__ g, const uint8_t *__restrict__ mat,
                                                     const uint8_t *__restrict__ flags, const T *__restrict__ jc,
                                                     T *__restrict__ H, FilmGeom G, FilmLaw law,
                                                     const IterState *__restrict__ it, int warm,
@@ -142,10 +151,10 @@ __global__ void __launch_bounds__(kStencilThreads) MAG_WAVES_PER_EU(sizeof(T) ==
     if (SPECTRAL && (fl[k] & 1)) {
       h = hw[k];
     } else if (fl[k] & 1) {
-      const T exq = film_edge_e<T>(g, mat, jc, G, law, p, q, 0);
-      const T exm = film_edge_e<T>(g, mat, jc, G, law, p, q - 1, 0);
-      const T eyp = film_edge_e<T>(g, mat, jc, G, law, p, q, 1);
-      const T eym = film_edge_e<T>(g, mat, jc, G, law, p - 1, q, 1);
+      const T exq = film_edge_e<T, P2>(g, mat, jc, G, law, p, q, 0);
+      const T exm = film_edge_e<T, P2>(g, mat, jc, G, law, p, q - 1, 0);
+      const T eyp = film_edge_e<T, P2>(g, mat, jc, G, law, p, q, 1);
+      const T eym = film_edge_e<T, P2>(g, mat, jc, G, law, p - 1, q, 1);
       const double curl = ((double)eyp - (double)eym) * G.idx - ((double)exq - (double)exm) * G.idy;
       h = (T)(-curl);
       H[i] = h;
@@ -458,7 +467,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
     const int k = j + rho * TT;
-    const int km = (M - k) & (M - 1);
+    const int km = k == 0 ? 0 : M - k;
     const cx<T> zk = v[rho];
     const cx<T> zm = conj(xch[km]);
     const cx<T> sum = zk + zm, dif = zk - zm;
@@ -598,7 +607,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
     const int k = j + rho * TT;
-    const int km = (M - k) & (M - 1);
+    const int km = k == 0 ? 0 : M - k;
     const cx<T> zk = v[rho];
     const cx<T> zm = conj(xch[km]);
     const cx<T> sum = zk + zm, dif = zk - zm;
@@ -750,7 +759,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
     const int k = j + rho * TT;
-    const int km = (M - k) & (M - 1);
+    const int km = k == 0 ? 0 : M - k;
     const cx<T> zk = v[rho];
     const cx<T> zm = conj(xch[km]);
     const cx<T> sum = zk + zm, dif = zk - zm;
@@ -980,7 +989,7 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     const int k = j + rho * TT;
     const T m0 = mult(kxx + ky2[rho]);
     if (packed) {
-      const cx<T> zm = conj(xch[lidx((NY - k) & (NY - 1))]);
+      const cx<T> zm = conj(xch[lidx(k == 0 ? 0 : NY - k)]);
       const T mm = mult(kxm + ky2[rho]);
       const T hp = (T)0.5 * (m0 + mm), hm = (T)0.5 * (m0 - mm);
       v[rho] = {hp * v[rho].x + hm * zm.x, hp * v[rho].y + hm * zm.y};
@@ -1071,7 +1080,7 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
   // i (hp Z + hm conj Z[-k]) with hp = (s0 + sM) / 2, hm = (s0 - sM) / 2; i s0 Z off the packed pencil
   auto apply = [&](const cx<T> &z, int k, T s0, T sm) -> cx<T> {
     if (packed) {
-      const cx<T> zm = conj(xch[lidx((NY - k) & (NY - 1))]);
+      const cx<T> zm = conj(xch[lidx(k == 0 ? 0 : NY - k)]);
       const T hp = (T)0.5 * (s0 + sm), hm = (T)0.5 * (s0 - sm);
       return {-(hp * z.y + hm * zm.y), hp * z.x + hm * zm.x};
     }
@@ -1208,7 +1217,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 #pragma unroll
     for (int rho = 0; rho < RMAX; ++rho) {
       const int k = j + rho * TT;
-      const int km = (M - k) & (M - 1);
+      const int km = k == 0 ? 0 : M - k;
       const cx<T> zk = vv[rho];
       const cx<T> zm = conj(xch[km]);
       const cx<T> sum = zk + zm, dif = zk - zm;
@@ -1500,6 +1509,11 @@ static FilmGeom fgeom(mag_ctx *c) {
 #define FILM_SWITCH_M(M_, ...)                            \
   switch (M_) {                                            \
     case 8: { constexpr int MM = 8; __VA_ARGS__; } break;         \
+    case 24: { constexpr int MM = 24; __VA_ARGS__; } break;       \
+    case 48: { constexpr int MM = 48; __VA_ARGS__; } break;       \
+    case 96: { constexpr int MM = 96; __VA_ARGS__; } break;       \
+    case 192: { constexpr int MM = 192; __VA_ARGS__; } break;     \
+    case 384: { constexpr int MM = 384; __VA_ARGS__; } break;     \
     case 16: { constexpr int MM = 16; __VA_ARGS__; } break;       \
     case 32: { constexpr int MM = 32; __VA_ARGS__; } break;       \
     case 64: { constexpr int MM = 64; __VA_ARGS__; } break;       \
@@ -1513,6 +1527,11 @@ static FilmGeom fgeom(mag_ctx *c) {
 #define FILM_SWITCH_N(N_, ...)                            \
   switch (N_) {                                            \
     case 16: { constexpr int NN = 16; __VA_ARGS__; } break;       \
+    case 48: { constexpr int NN = 48; __VA_ARGS__; } break;       \
+    case 96: { constexpr int NN = 96; __VA_ARGS__; } break;       \
+    case 192: { constexpr int NN = 192; __VA_ARGS__; } break;     \
+    case 384: { constexpr int NN = 384; __VA_ARGS__; } break;     \
+    case 768: { constexpr int NN = 768; __VA_ARGS__; } break;     \
     case 32: { constexpr int NN = 32; __VA_ARGS__; } break;       \
     case 64: { constexpr int NN = 64; __VA_ARGS__; } break;       \
     case 128: { constexpr int NN = 128; __VA_ARGS__; } break;     \
@@ -1830,14 +1849,20 @@ static int film_stencil_pass(mag_ctx *c, const double *state, int warm) {
   const int nbs = film_stencil_blocks(c);
   if (c->deriv == 0) {
     ProfLaunch ps(c, K_FILM_STENCIL);
-    MAG_TIMED_LAUNCH(ps, (film_stencil<T, false>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
-                     c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm,
-                     film_regions<T>(c).X);
+    const bool p2 = !(G.nx & (G.nx - 1)) && !(G.ny & (G.ny - 1));
+    if (p2)
+      MAG_TIMED_LAUNCH(ps, (film_stencil<T, false, true>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state,
+                       c->d_mat, c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm,
+                       film_regions<T>(c).X);
+    else
+      MAG_TIMED_LAUNCH(ps, (film_stencil<T, false, false>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state,
+                       c->d_mat, c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm,
+                       film_regions<T>(c).X);
     return MAG_OK;
   }
   if (int rc = film_spectral_film_values<T>(c, state)) return rc;
   ProfLaunch ps(c, K_FILM_STENCIL);
-  MAG_TIMED_LAUNCH(ps, (film_stencil<T, true>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
+  MAG_TIMED_LAUNCH(ps, (film_stencil<T, true, false>), dim3(nbs), dim3(kStencilThreads), 0, c->stream, state, c->d_mat,
                    c->d_flags, reinterpret_cast<const T *>(c->d_jc), f.H, G, law, c->d_it, warm, film_regions<T>(c).X);
   MAG_HIP(c, hipGetLastError());
   return MAG_OK;
@@ -2233,7 +2258,7 @@ int film_domain(mag_ctx *c) {
   const long long n = c->nnode;
   const std::vector<uint8_t> &m = c->h_mat;
   std::vector<uint8_t> fl(n, 0);
-  auto F = [&](int p, int q) { return m[(long long)(q & (ny - 1)) * nx + (p & (nx - 1))] != 0; };
+  auto F = [&](int p, int q) { return m[(long long)((q % ny + ny) % ny) * nx + (p % nx + nx) % nx] != 0; };
   long long nin = 0;
   for (int q = 0; q < ny; ++q)
     for (int p = 0; p < nx; ++p) {

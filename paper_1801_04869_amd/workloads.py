@@ -45,6 +45,17 @@ def film_ring(nx, ny, Lx, Ly, r_in, r_out):
     return m
 
 
+def film_rect_hole(nx, ny, Lx, Ly, ax, ay, cx, cy, r):
+    """Rectangle |x| <= ax, |y| <= ay with the circular hole
+    (x - cx)^2 + (y - cy)^2 <= r^2 filled by a normal conductor (the film of
+    Sec. 2.3, Fig. 3: ax = 1.5, ay = 1, centre (0.5, 0.25), r = 0.5)."""
+    m = film_rect(nx, ny, Lx, Ly, ax, ay)
+    xc, yc = cell_centres(nx, Lx), cell_centres(ny, Ly)
+    hole = (xc[None, :] - cx) ** 2 + (yc[:, None] - cy) ** 2 <= r ** 2
+    m[hole & (m == SC)] = OHMIC
+    return m
+
+
 def film_slot(nx, ny, Lx, Ly, half, slot_cells):
     """Square |x|,|y| <= half minus the slot {x >= 0, |y| <= slot_cells*dy/2},
     open to the free space (the slot belongs to the free space)."""
@@ -136,6 +147,9 @@ def workload(name):
 
     film-128      64x64-cell square film in a 128^2 periodic grid, [-2,2]^2
     film-2048-ring / film-2048-slot   1024^2-cell ring / slotted square in 2048^2
+    film-768x512-hole  rectangular film with a circular hole (Sec. 2.3, Fig. 3):
+                  768x512 grid on |x| <= 2.25, |y| <= 1.5, n = 50, rho_out = 500
+                  in the hole and outside, h_e = t
     bulk-64       32^3-cell cube in a 64^3 grid, [-2,2]^3, n = 25
     bulk-256      128^3-cell cube in a 256^3 grid, [-2,2]^3, n = 50, tilted field,
                   log-normal jc (s = 0.15, correlation 6 cells)
@@ -148,6 +162,11 @@ def workload(name):
         return dict(dim=2, n=(2048, 2048), L=(2.0, 2.0), nexp=30.0, rho_out=500.0,
                     jc=dict(s=0.2, ell=8.0, seed=1801 if name.endswith("ring") else 1802),
                     field=dict(kind=1, dir=(0, 0, 1), amp=0.8, omega=1.25, rate=1.0))
+    if name == "film-768x512-hole":
+        # lambda: the relaxation of (12) below 2 / mu_max at this resolution
+        return dict(dim=2, n=(768, 512), L=(2.25, 1.5), nexp=50.0, rho_out=500.0, lam=0.4,
+                    hole=dict(ax=1.5, ay=1.0, cx=0.5, cy=0.25, r=0.5),
+                    field=dict(kind=0, dir=(0, 0, 1), amp=1.0, omega=1.0, rate=1.0))
     if name == "bulk-64":
         return dict(dim=3, n=(64, 64, 64), L=(2.0, 2.0, 2.0), half=(1.0, 1.0, 1.0), nexp=25.0,
                     field=dict(kind=0, dir=(0, 0, 1), amp=1.0, omega=1.0, rate=1.0))

@@ -18,6 +18,9 @@ def film_case(nx, ny, L=(2.0, 2.0), kind="rect", n=19.0, jc_s=0.0, seed=1801, rh
         mat = W.film_slot(nx, ny, Lx, Ly, 0.5 * Lx, 8)
     elif kind == "disk":
         mat = W.film_disk(nx, ny, Lx, Ly, 0.5 * Lx)
+    elif kind == "hole":
+        # the geometry of Sec. 2.3, Fig. 3 scaled to the box [-Lx, Lx] x [-Ly, Ly]
+        mat = W.film_rect_hole(nx, ny, Lx, Ly, Lx / 1.5, Ly / 1.5, Lx / 4.5, Ly / 6.0, Ly / 3.0)
     else:
         raise KeyError(kind)
     jc = W.lognormal_jc((ny, nx), jc_s, 4.0, seed) if jc_s > 0 else None

@@ -175,6 +175,16 @@ def main(path, which):
                   ("spectral", film_case(32, 32, L=(1.0, 1.0), kind="disk"), 0, 0, sp),
                   ("spectral", film_case(32, 32, L=(1.0, 1.0), kind="disk"), 2, 0, sp),
                   ("spectral", film_case(16, 1024, L=(0.25, 2.0), kind="offrect", jc_s=0.2), 1, 2, sp)]
+    if which in ("radix3", "all"):
+        # grids of 3 * 2^k nodes (radix-12 first stage): both aspect ratios,
+        # every precision, both film forms, the stop test
+        sp = "spectral"
+        cases += [("radix3", film_case(96, 64, L=(2.25, 1.5), kind="hole", jc_s=0.2, rho_out=20.0), 0, 2),
+                  ("radix3", film_case(64, 96, L=(1.5, 2.25), kind="offrect", jc_s=0.2), 1, 3),
+                  ("radix3", film_case(48, 48, L=(1.0, 1.0), kind="disk"), 2, 2),
+                  ("radix3", film_case(96, 48, L=(2.0, 1.0), kind="offrect", jc_s=0.2), 0, 0),
+                  ("radix3", film_case(96, 64, L=(2.25, 1.5), kind="hole", jc_s=0.2, rho_out=20.0), 1, 2, sp),
+                  ("radix3", film_case(48, 96, L=(1.0, 2.0), kind="ring", rho_out=20.0), 0, 0, sp)]
     for entry in cases:
         name, case, prec, fixed = entry[:4]
         deriv = entry[4] if len(entry) > 4 else "staggered"

@@ -32,7 +32,7 @@ def _libasan():
 @pytest.mark.slow
 @pytest.mark.skipif(os.environ.get("MAG_EMU") != "1",
                     reason="emulated-kernel runs take 5-15 min per case; MAG_EMU=1 runs them")
-@pytest.mark.parametrize("which", ["film", "spectral", "capture", "bulk", "bulk32"])
+@pytest.mark.parametrize("which", ["film", "spectral", "radix3", "capture", "bulk", "bulk32"])
 def test_emulated_kernels_in_bounds_and_match_oracle(which, tmp_path):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")

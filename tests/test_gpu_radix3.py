@@ -1,0 +1,196 @@
+"""GPU parity on film grids of 3 * 2^k nodes (radix-12 first stage of the
+row and column transforms) against the FP64 oracle, through the C ABI:
+both film forms (staggered differences and the spectral form of Sec. 2.2),
+every precision, fixed counts and the stop test, the observables, the VJP,
+the captured integrator, and the film with a circular hole of Sec. 2.3
+(Fig. 3) on its 768 x 512 grid.  Tolerances as for power-of-two grids:
+relative L2 1e-10 in FP64, 1e-4 in the mixed forms."""
+import numpy as np
+import pytest
+
+from tests._cases import film_case, make_gpu, make_oracle, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import adjoint, film  # noqa: E402
+from paper_1801_04869_amd import api  # noqa: E402
+from paper_1801_04869_amd import workloads as W  # noqa: E402
+
+TOL = {api.FP64: 1e-10, api.MIXED: 1e-4, api.MIXED_FINAL64: 1e-4}
+PRECS = [api.FP64, api.MIXED, api.MIXED_FINAL64]
+FORMS = ["staggered", "spectral"]
+
+
+def _gpu_rhs(ctx, state, t):
+    s = torch.from_numpy(np.ascontiguousarray(state)).cuda()
+    out = torch.empty_like(s)
+    st, it = ctx.rhs(s, t, out)
+    torch.cuda.synchronize()
+    return st, it, out.cpu().numpy()
+
+
+CASES = [
+    dict(nx=96, ny=64, L=(2.25, 1.5), kind="hole", jc_s=0.2, rho_out=20.0),
+    dict(nx=64, ny=96, L=(1.5, 2.25), kind="offrect", jc_s=0.2),
+    dict(nx=48, ny=48, L=(1.0, 1.0), kind="disk", n=30.0),
+    dict(nx=768, ny=16, L=(6.0, 0.125), kind="offrect", jc_s=0.2),
+    dict(nx=16, ny=768, L=(0.125, 6.0), kind="offrect", jc_s=0.2),
+    dict(nx=384, ny=768, L=(1.5, 3.0), kind="ring", rho_out=20.0),
+]
+
+
+def _case(ci):
+    kw = dict(CASES[ci])
+    return film_case(kw.pop("nx"), kw.pop("ny"), **kw)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_radix3_rhs_fixed_iterations(form, prec, ci):
+    case = _case(ci)
+    print("radix-3 fixed", case["n"], form, prec, flush=True)
+    ctx = make_gpu(case, prec, fixed=3, deriv=form)
+    prob = make_oracle(case, fixed=3, deriv=form)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.2)
+    ref, rit, rst = film.rhs(prob, case["state"], 0.2)
+    assert st == 0 and rst == 0 and it == rit == 3
+    assert rel_l2(out, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_radix3_rhs_converged_sequence(form):
+    """Stop test and warm start on the hole film at 192 x 128, FP64: the same
+    iteration counts and results as the oracle over three calls."""
+    case = film_case(192, 128, L=(2.25, 1.5), kind="hole", jc_s=0.2, rho_out=20.0)
+    ctx = make_gpu(case, api.FP64, deriv=form)
+    prob = make_oracle(case, deriv=form)
+    for k, t in enumerate([0.2, 0.21, 0.23]):
+        state = case["state"] * (1.0 + 0.01 * k)
+        st, it, out = _gpu_rhs(ctx, state, t)
+        ref, rit, rst = film.rhs(prob, state, t)
+        print("%s call %d: iterations GPU %d oracle %d, rel-L2 %.3e" % (form, k, it, rit, rel_l2(out, ref)),
+              flush=True)
+        assert st == 0 and rst == 0 and it == rit
+        assert rel_l2(out, ref) < 1e-10
+
+
+def _hole_case():
+    wl = W.workload("film-768x512-hole")
+    nx, ny = wl["n"]
+    Lx, Ly = wl["L"]
+    h = wl["hole"]
+    mat = W.film_rect_hole(nx, ny, Lx, Ly, h["ax"], h["ay"], h["cx"], h["cy"], h["r"])
+    g = W.film_snapshot(mat, 2 * Lx / nx, delta=0.15, seed=1806)
+    return dict(dim=2, n=(nx, ny, 1), L=(Lx, Ly, 1.0), mat=mat, jc=None, state=g, nexp=wl["nexp"],
+                rho_out=wl["rho_out"], field=wl["field"])
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("prec", PRECS)
+def test_hole_film_768x512(form, prec):
+    """The film of Sec. 2.3, Fig. 3 (rectangle with a circular hole filled by a
+    normal conductor, rho_out = 500, n = 50, 768 x 512 grid), 4 inner
+    iterations on a Bean-like snapshot, every node compared with the oracle."""
+    case = _hole_case()
+    ctx = make_gpu(case, prec, lam=0.4, fixed=4, deriv=form)
+    prob = make_oracle(case, lam=0.4, fixed=4, deriv=form)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.3)
+    ref, rit, rst = film.rhs(prob, case["state"], 0.3)
+    e = rel_l2(out, ref)
+    print("768x512 hole film, %s, precision %d: rel-L2 %.3e" % (form, prec, e), flush=True)
+    assert st == 0 and rst == 0 and it == rit == 4
+    assert e < TOL[prec]
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_hole_film_converged_right_hand_side(form):
+    """The same film with the stop test of Sec. 2.3 (FP64): same count and
+    result as the oracle.  lambda = 0.4: with 0.7 the relaxed iteration
+    diverges at this resolution in both forms (the oracle does not stop
+    within 150 evaluations; with 0.4 it stops after 16 / 19)."""
+    case = _hole_case()
+    ctx = make_gpu(case, api.FP64, lam=0.4, deriv=form)
+    prob = make_oracle(case, lam=0.4, deriv=form)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.3)
+    ref, rit, rst = film.rhs(prob, case["state"], 0.3)
+    print("768x512 hole film converged, %s: %d / %d iterations, rel-L2 %.3e" % (form, it, rit, rel_l2(out, ref)),
+          flush=True)
+    assert st == 0 and rst == 0 and it == rit
+    assert rel_l2(out, ref) < 1e-10
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+def test_radix3_observables(form, prec):
+    case = film_case(96, 64, L=(2.25, 1.5), kind="hole", jc_s=0.2, rho_out=20.0)
+    ctx = make_gpu(case, prec, fixed=2, deriv=form)
+    prob = make_oracle(case, fixed=2, deriv=form)
+    s = torch.from_numpy(case["state"]).cuda()
+    hz, j, m = ctx.observe(s, 0.3)
+    rhz, (rjx, rjy), rmz = film.observe(prob, case["state"], 0.3)
+    tol = 1e-10 if prec == api.FP64 else 1e-5
+    jj = j.cpu().numpy()
+    assert rel_l2(hz.cpu().numpy(), rhz) < tol
+    assert rel_l2(jj[0], rjx) < tol and rel_l2(jj[1], rjy) < tol
+    assert abs(m[2] - rmz) <= 1e-12 * abs(rmz)
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+def test_radix3_vjp(prec):
+    """Vector-Jacobian product (staggered form, fixed count) on the 96 x 64
+    hole film against the oracle's transpose."""
+    case = film_case(96, 64, L=(2.25, 1.5), kind="hole", jc_s=0.2, rho_out=20.0)
+    ctx = make_gpu(case, prec, fixed=3)
+    prob = make_oracle(case, fixed=3)
+    ybar = np.random.default_rng(7).standard_normal(case["state"].shape)
+    s = torch.from_numpy(case["state"]).cuda()
+    yb = torch.from_numpy(ybar).cuda()
+    gb, jb = torch.empty_like(s), torch.empty_like(s)
+    assert ctx.rhs_vjp(s, 0.2, yb, gb, jb) == api.OK
+    rg, rj, _, _ = adjoint.film_rhs_vjp(prob, case["state"], 0.2, ybar)
+    assert rel_l2(gb.cpu().numpy(), rg) < TOL[prec]
+    assert rel_l2(jb.cpu().numpy(), rj) < TOL[prec]
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_radix3_captured_integration_matches_host_driven(form):
+    """The hole film at 192 x 128 (h_e = t, 3 inner iterations) integrated to
+    t = 0.1 by the captured driver and by the host-driven one: the same
+    accepted steps and state."""
+    case = film_case(192, 128, L=(2.25, 1.5), kind="hole", n=50.0, rho_out=500.0)
+    y0 = np.zeros_like(case["state"])
+    ctx = make_gpu(case, api.FP64, fixed=3, deriv=form)
+    yh = torch.from_numpy(y0.copy()).cuda()
+    nh, _ = ctx.integrate(yh, 0.0, 0.1)
+    ctx.close()
+    ctx = make_gpu(case, api.FP64, fixed=3, deriv=form)
+    yc = torch.from_numpy(y0.copy()).cuda()
+    na, nr, tr = ctx.integrate_captured(yc, 0.0, 0.1, chunk=8)
+    e = rel_l2(yc.cpu().numpy(), yh.cpu().numpy())
+    print("%s: host %d steps, captured %d accepted %d rejected; rel-L2 %.3e" % (form, nh, na, nr, e), flush=True)
+    assert abs(na - nh) <= 1 and tr == 0.1
+    assert e < (1e-10 if na == nh else 1e-5)
+
+
+def test_grid_sizes_accepted_and_refused():
+    ok = [(48, 48), (768, 512), (96, 2048), (2048, 384)]
+    bad = [(36, 48), (1536, 512), (48, 1536), (80, 64), (12, 16)]
+    for nx, ny in ok:
+        c = api.Context(2, api.FP64)
+        c.set_grid(nx, ny, 1, 1.0, 1.0)
+        c.close()
+    for nx, ny in bad:
+        c = api.Context(2, api.FP64)
+        with pytest.raises(api.MagError) as e:
+            c.set_grid(nx, ny, 1, 1.0, 1.0)
+        assert e.value.code == api.E_ARG
+        c.close()
+    c = api.Context(3, api.FP64)
+    with pytest.raises(api.MagError):
+        c.set_grid(48, 48, 48, 1.0, 1.0, 1.0)
+    c.close()

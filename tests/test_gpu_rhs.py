@@ -338,7 +338,7 @@ def test_film_integrate_replayed_steps_match_oracle():
 def test_argument_and_state_errors():
     c = api.Context(2, api.FP64)
     with pytest.raises(api.MagError) as e:
-        c.set_grid(48, 32, 1, 1, 1)
+        c.set_grid(40, 32, 1, 1, 1)   # neither 2^k nor 3 * 2^k
     assert e.value.code == api.E_ARG
     with pytest.raises(api.MagError) as e:
         c.set_grid(32, 32, 2, 1, 1)
