@@ -21,11 +21,12 @@ def _grid(nx, ny, Lx, Ly, p):
     return x[None, :], y[:, None]
 
 
+@pytest.mark.parametrize("nx,ny", [(32, 16), (48, 24)])
 @pytest.mark.parametrize("mx,my", [(3, 2), (1, 0), (0, 5), (7, 3)])
-def test_spectral_derivative_of_a_plane_wave(mx, my):
+def test_spectral_derivative_of_a_plane_wave(mx, my, nx, ny):
     """d/dx and d/dy of g = cos(k.x + phi): -k_a exp(-|k|^2 s^2 / 2) sin(k.x + phi),
-    s = sqrt(dx^2 + dy^2) by default."""
-    nx, ny, Lx, Ly = 32, 16, 2.0, 1.0
+    s = sqrt(dx^2 + dy^2) by default (a power-of-two grid and one of 3 * 2^k)."""
+    Lx, Ly = 2.0, 1.0
     p = film.FilmProblem(nx, ny, Lx, Ly, np.zeros((ny, nx), np.uint8), deriv="spectral")
     s = np.sqrt(p.dx ** 2 + p.dy ** 2)
     assert abs(p.deriv_sigma - s) < 1e-15
@@ -91,13 +92,15 @@ def test_node_classes_and_node_jc():
             assert p.in_node[q, pp] == all(m[c] != 0 for c in cells)
 
 
-def test_spectral_converged_rhs_solves_free_space_conditions():
+@pytest.mark.parametrize("nx,ny", [(16, 16), (24, 12)])
+def test_spectral_converged_rhs_solves_free_space_conditions(nx, ny):
     """The converged iteration in the spectral form satisfies gdot = 0 in
     free space up to the constant C, and (10), for the film values of the
-    spectral (9): a dense linear solve in the free-space unknowns."""
-    nx = ny = 16
-    m = W.film_rect(nx, ny, 2.0, 2.0, 1.0, 1.0)
-    p = film.FilmProblem(nx, ny, 2.0, 2.0, m, tol=1e-13, max_inner=20000, n=5.0, deriv="spectral",
+    spectral (9): a dense linear solve in the free-space unknowns (a
+    power-of-two grid and one of 3 * 2^k nodes)."""
+    Ly = 2.0 * ny / nx
+    m = W.film_rect(nx, ny, 2.0, Ly, 1.0, 0.5 * Ly)
+    p = film.FilmProblem(nx, ny, 2.0, Ly, m, tol=1e-13, max_inner=20000, n=5.0, deriv="spectral",
                          field=AppliedField(rate=0.8))
     g = W.film_snapshot(p.material, p.dx, delta=0.3, seed=5)
     gd, it, st = film.rhs(p, g, 0.2)
