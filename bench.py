@@ -389,6 +389,73 @@ def hole_film_lines(a):
     return out
 
 
+def paper_runs():
+    """The paper's timed whole runs in its own discretisation (the spectral
+    form, FP64, adaptive BS23 with rtol 1e-3 / atol 1e-6, the stop test of
+    Sec. 2.3): the disk of Table 1 (radius 1 in [-2, 2]^2, n = 1000,
+    rho_out = 1, h_e = t to 0.5) at 128^2, 256^2 and 512^2 with the L1
+    deviation of |j| from the Bean solution, and the film with a hole of
+    Sec. 2.3, Fig. 3 to t = 0.4.  The paper's figures (Matlab on one CPU)
+    are context, not targets."""
+    import torch
+    from oracle import bean
+    from paper_1801_04869_amd import api
+    from paper_1801_04869_amd import workloads as W
+
+    def run(mat, n, L, nexp, rho_out, lam, prec, t_end):
+        c = api.Context(2, prec)
+        c.set_grid(n[0], n[1], 1, *L)
+        c.set_derivatives(api.SPECTRAL)
+        c.set_domain(torch.from_numpy(mat).cuda())
+        c.set_params(None, 1.0, nexp, 1.0, rho_out)
+        c.set_solver(lam, 2e-4, 100, 0)
+        c.set_field(api.RAMP, (0.0, 0.0, 1.0), 1.0, 1.0, 1.0)
+        g = torch.zeros((n[1], n[0]), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, _ = c.integrate(g, 0.0, t_end, 1e-3, 1e-6)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        n_rhs, n_inner = c.stats()
+        _, j, (_, _, mz) = c.observe(g, t_end)
+        c.close()
+        return g, j.cpu().numpy(), dict(wall_s=round(wall, 3), steps=steps, rhs=n_rhs,
+                                        mean_inner_iters=round(n_inner / max(n_rhs, 1), 2), m_z=mz)
+
+    out = dict(form="spectral (Sec. 2.2), FP64 unless named, BS23 rtol 1e-3 atol 1e-6, stop test 2e-4",
+               paper_hardware="Matlab R2017a on one Intel Core i5-2400 (context only)")
+    table1 = {}
+    for N, lam, pmin, pdj in ((128, 0.7, 0.2, 2.2), (256, 0.7, 2.0, 1.0), (512, 0.5, 49.0, 0.9)):
+        mat = W.film_disk(N, N, 2.0, 2.0, 1.0)
+        g, j, r = run(mat, (N, N), (2.0, 2.0), 1000.0, 1.0, lam, api.FP64, 0.5)
+        x = -2.0 + (4.0 / N) * np.arange(N)
+        rad = np.hypot(*np.meshgrid(x, x))
+        inside = rad < 1.0
+        jb = np.abs(bean.disk_current(rad[inside], 1.0, 0.5))
+        r["dj_percent"] = round(100 * float(np.abs(np.hypot(j[0], j[1])[inside] - jb).sum() / jb.sum()), 2)
+        r.update(lambda_=lam, paper_wall_min=pmin, paper_dj_percent=pdj)
+        table1["disk-%d" % N] = r
+        print("[bench] Table 1 disk %d^2: %.2f s (paper %.1f min), dj %.2f %% (paper %.1f %%)" %
+              (N, r["wall_s"], pmin, r["dj_percent"], pdj), file=sys.stderr, flush=True)
+    out["table1_disk"] = table1
+    wl = W.workload("film-768x512-hole")
+    h = wl["hole"]
+    mat = W.film_rect_hole(*wl["n"], *wl["L"], h["ax"], h["ay"], h["cx"], h["cy"], h["r"])
+    hole = {}
+    states = {}
+    for name, prec in (("fp64", api.FP64), ("mixed", api.MIXED)):
+        g, j, r = run(mat, wl["n"], wl["L"], wl["nexp"], wl["rho_out"], wl["lam"], prec, 0.4)
+        states[name] = g.cpu().numpy()
+        r.update(lambda_=wl["lam"], paper_wall_min=63.0)
+        hole[name] = r
+        print("[bench] hole film 768x512 to t = 0.4, %s: %.2f s, %d steps (paper 63 min)" %
+              (name, r["wall_s"], r["steps"]), file=sys.stderr, flush=True)
+    hole["mixed_vs_fp64_g_rel_l2"] = float(np.linalg.norm(states["mixed"] - states["fp64"]) /
+                                           np.linalg.norm(states["fp64"]))
+    out["hole_film_768x512_t04"] = hole
+    return out
+
+
 def converged_window(prec, wl, mat, jc, lam, warm_attempts, attempts, deriv="staggered"):
     """Right-hand sides of an adaptive BS23 run with the stop test: from the
     virgin state g = 0 at t = 0, `warm_attempts` step attempts (untimed) bring
@@ -662,6 +729,7 @@ def main():
     # the film with a circular hole of Sec. 2.3, Fig. 3 (768 x 512, radix-12 row transforms)
     if not a.quick:
         line["film_768x512_hole"] = hole_film_lines(a)
+        line["paper_runs"] = paper_runs()
     line["adjoint_forward_ratio_film"] = round(m["vjp_ms"] / m["ms_per_step"], 3)
     line["bs23_step_ms"] = round(m["step_ms"], 4)
     line["bs23_step_over_3_rhs"] = round(m["step_ms"] * m["value_stream"] / 3e3, 3)
