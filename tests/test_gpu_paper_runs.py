@@ -30,22 +30,60 @@ def _run(mat, n, L, nexp, rho_out, lam, t_end, prec=api.FP64):
     return steps, g.cpu().numpy(), j.cpu().numpy(), m
 
 
-def test_table1_disk_256():
-    """Table 1, 256^2 (the paper: L1 deviation of |j| 1.0 %; measured here
-    1.9 %, and 3.7 % at 128^2, 1.5 % at 512^2: the deviation falls with the
-    grid as the paper's does)."""
-    N = 256
+_BEAN_HZ = {}
+
+
+def _bean_hz(r, ha=0.5):
+    """The Bean disk's h_z at radii r (radius 1): zero inside the flux front,
+    elsewhere interpolated from the oracle's loop superposition on radii
+    clustered toward the edge, where h_z is log-singular."""
+    if ha not in _BEAN_HZ:
+        a = bean.disk_front(1.0, ha)
+        u = np.linspace(0.0, 1.0, 121)
+        inner = np.concatenate([a + (1.0 - a) * (1.0 - (1.0 - u[:-1]) ** 2), [1.0 - 1e-6]])
+        outer = 1.0 + 1e-6 + (2.0 * np.sqrt(2.0) - 1.0) * u[:61] ** 2 * 1.0001
+        _BEAN_HZ[ha] = (inner, bean.disk_field(inner, 1.0, ha, tol=1e-8), outer,
+                        bean.disk_field(outer, 1.0, ha, tol=1e-8))
+    ri, hi, ro, ho = _BEAN_HZ[ha]
+    return np.where(r < ri[0], 0.0, np.where(r < 1.0, np.interp(r, ri, hi), np.interp(r, ro, ho)))
+
+
+# (grid, lambda, bounds on delta j, delta h_z over the disk, delta h_z over the
+# domain).  The paper: delta j 1.0 / 0.9 %, delta h_z 7.1 / 4.0 % at 256^2 /
+# 512^2, without naming the region of delta h_z.  Measured here: delta j 1.90 /
+# 1.51 %, delta h_z 17.1 / 12.1 % over the disk and 3.6 / 3.0 % over the
+# domain; the bounds leave about 20 % above the measured values.
+@pytest.mark.parametrize("N,lam,bj,bh,bhd", [(256, 0.7, 0.023, 0.21, 0.044), (512, 0.5, 0.019, 0.15, 0.036)])
+def test_table1_disk(N, lam, bj, bh, bhd):
+    """Table 1: L1 deviations of |j| (nodes inside the disk) and of h_z (nodes
+    inside the disk, and all nodes of the domain) from the Bean solution after
+    the field rise to h_e = 0.5."""
+    import warnings
     mat = W.film_disk(N, N, 2.0, 2.0, 1.0)
-    print("disk 256^2, n = 1000, spectral form: integrating to h_e = 0.5", flush=True)
-    steps, g, j, _ = _run(mat, (N, N), (2.0, 2.0), 1000.0, 1.0, 0.7, 0.5)
+    print("disk %d^2, n = 1000, spectral form: integrating to h_e = 0.5" % N, flush=True)
+    steps, g, j, _ = _run(mat, (N, N), (2.0, 2.0), 1000.0, 1.0, lam, 0.5)
+    c = api.Context(2, api.FP64)
+    c.set_grid(N, N, 1, 2.0, 2.0)
+    c.set_derivatives(api.SPECTRAL)
+    c.set_domain(torch.from_numpy(mat).cuda())
+    c.set_field(api.RAMP, (0.0, 0.0, 1.0), 1.0, 1.0, 1.0)
+    hz, _, _ = c.observe(torch.from_numpy(g).cuda(), 0.5, want_hz=True, want_j=False)
+    hz = hz.cpu().numpy()
     x = -2.0 + (4.0 / N) * np.arange(N)
     r = np.hypot(*np.meshgrid(x, x))
     inside = r < 1.0
     jb = np.abs(bean.disk_current(r[inside], 1.0, 0.5))
     dj = np.abs(np.hypot(j[0], j[1])[inside] - jb).sum() / jb.sum()
-    print("steps %d, L1 deviation of |j| %.2f %%" % (steps, 100 * dj), flush=True)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        hb_all = _bean_hz(r)
+    hb = hb_all[inside]
+    dh = np.abs(hz[inside] - hb).sum() / np.abs(hb).sum()
+    dh_d = np.abs(hz - hb_all).sum() / np.abs(hb_all).sum()
+    print("steps %d, L1 deviation of |j| %.2f %%, of h_z %.2f %% (disk), %.2f %% (domain)" %
+          (steps, 100 * dj, 100 * dh, 100 * dh_d), flush=True)
     assert steps > 500
-    assert dj < 0.025
+    assert dj < bj and dh < bh and dh_d < bhd
 
 
 def test_hole_film_to_t04():

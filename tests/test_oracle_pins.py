@@ -132,23 +132,7 @@ def _ring_hz(rho, r):
 
 
 def _disk_hz(r0, R, ha):
-    """Applied field plus the Biot-Savart field of the Bean disk current at
-    radius r0 in the film plane (superposition of coaxial rings)."""
-    a = bean.disk_front(R, ha)
-    J = lambda rho: float(bean.disk_current(np.array([rho]), R, ha)[0])
-    pts = sorted({r0, a, R})
-    k_part, e_part = 0.0, 0.0
-    lo = 0.0
-    for hi in pts + ([] if pts[-1] >= R else [R]):
-        if hi <= lo or hi > R:
-            continue
-        k_part += integrate.quad(lambda s: J(s) * _ring_hz(s, r0)[0], lo, hi, limit=400,
-                                 epsabs=1e-13, epsrel=1e-12)[0]
-        lo = hi
-    # principal value of int J(s) E(s) / (s - r0) ds over [0, R]
-    e_part = integrate.quad(lambda s: J(s) * _ring_hz(s, r0)[1], 0.0, R, weight="cauchy", wvar=r0,
-                            limit=400, epsabs=1e-13, epsrel=1e-12)[0]
-    return ha + (k_part + e_part) / (2 * np.pi)
+    return float(bean.disk_field(np.array([r0]), R, ha)[0])
 
 
 @pytest.mark.parametrize("ha", [0.3, 0.6])
