@@ -433,6 +433,13 @@ def paper_runs():
         print("[bench] Table 1 disk %d^2: %.2f s, %d steps (paper %.1f min)" % (N, r["wall_s"], r["steps"], pmin),
               file=sys.stderr, flush=True)
     out["table1_disk"] = table1
+    # the rectangle of Sec. 2.3, Fig. 2 (the paper gives no time for it)
+    g, j, r = run(W.film_rect(1024, 256, 4.0, 1.0, 3.2, 0.5), (1024, 256), (4.0, 1.0), 1000.0, 1.0, 0.4,
+                  api.FP64, 0.5)
+    r.update(lambda_=0.4)
+    out["strip_1024x256"] = r
+    print("[bench] strip 1024x256 to h_e = 0.5: %.2f s, %d steps" % (r["wall_s"], r["steps"]), file=sys.stderr,
+          flush=True)
     wl = W.workload("film-768x512-hole")
     h = wl["hole"]
     mat = W.film_rect_hole(*wl["n"], *wl["L"], h["ax"], h["ay"], h["cx"], h["cy"], h["r"])
