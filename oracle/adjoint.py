@@ -34,7 +34,9 @@ the forward iteration's error, so the converged (fixed-point) adjoint is the
 same recursion run until the free-space part is negligible.
 
 The film part of x_bar is then pulled back through eq. (9), the power law and
-eq. (2), and through the edge jc = mean of the two cells to the per-cell map.
+eq. (2), and through the edge jc = mean of the two cells to the per-cell map
+(staggered form), or through the node quantities of the spectral form and the
+node jc = mean of the four cells (film_spectral_vjp).
 """
 import numpy as np
 
@@ -94,6 +96,40 @@ def film_stencil_vjp(prob, g, hbar):
     return gbar, jcbar
 
 
+def film_spectral_vjp(prob, g, hbar):
+    """Transpose of g -> dh_in in the spectral form of Sec. 2.2 applied to
+    hbar (zero off the film).  Returns (g_bar, jc_cell_bar).
+
+    The forward: j = (D_y g, -D_x g) at the nodes, e = rho(|j|) j, dh_in =
+    -(D_x e_y - D_y e_x).  A filtered derivative D_a has the symbol
+    i k_a exp(-|k|^2 s^2 / 2), odd and imaginary, so as a real operator its
+    transpose is -D_a.  At power-law nodes de/dj = rho I + rho (n-1) j j^T / |j|^2
+    and de/djc = -n e / jc; elsewhere e = rho_out j.  The node jc is the mean of
+    the node's four cells."""
+    jx, jy = film.sheet_current_nodes(prob, g)
+    s = np.sqrt(jx ** 2 + jy ** 2)
+    nm1 = prob.n - 1.0
+    jce = prob.jc_node
+    rho_pl = (prob.e0 / jce) * (s / jce) ** nm1
+    sd = film.spectral_derivative
+    # dh_in = D_y e_x - D_x e_y
+    ebar_x = -sd(hbar, prob.DY)
+    ebar_y = sd(hbar, prob.DX)
+    jdot = jx * ebar_x + jy * ebar_y
+    pos = s > 0
+    fac = np.where(pos, rho_pl * nm1 * jdot / np.where(pos, s * s, 1.0), 0.0)
+    sc = prob.sc_node
+    jbar_x = np.where(sc, rho_pl * ebar_x + fac * jx, prob.rho_out * ebar_x)
+    jbar_y = np.where(sc, rho_pl * ebar_y + fac * jy, prob.rho_out * ebar_y)
+    # j_x = D_y g, j_y = -D_x g
+    gbar = -sd(jbar_x, prob.DY) + sd(jbar_y, prob.DX)
+    # node (p, q) takes the mean jc of cells (p,q), (p-1,q), (p,q-1), (p-1,q-1),
+    # so cell (p, q) collects a quarter of nodes (p,q), (p+1,q), (p,q+1), (p+1,q+1)
+    cnode = np.where(sc, -prob.n * rho_pl * jdot / jce, 0.0)
+    jcbar = 0.25 * (cnode + shift(cnode, 1, 1) + shift(cnode, 0, 1) + shift(shift(cnode, 1, 1), 0, 1))
+    return gbar, jcbar
+
+
 def film_iteration_vjp(prob, ybar, k=None):
     """x_bar on the film nodes for the cotangent ybar of gdot.
 
@@ -148,7 +184,10 @@ def film_rhs_vjp(prob, g, t, ybar, jc0=1.0):
     t does not enter: dh_e/dt only shifts the iteration by constants."""
     k = prob.fixed_iters if prob.fixed_iters > 0 else None
     hbar, count, status = film_iteration_vjp(prob, ybar, k)
-    gbar, jcbar = film_stencil_vjp(prob, g, hbar)
+    if prob.deriv == "spectral":
+        gbar, jcbar = film_spectral_vjp(prob, g, hbar)
+    else:
+        gbar, jcbar = film_stencil_vjp(prob, g, hbar)
     return gbar, jc0 * jcbar, count, status
 
 

@@ -141,7 +141,7 @@ struct mag_ctx {
   double dsigma = -1;             // spectral form: Gaussian width sigma (< 0: sqrt(dx^2 + dy^2))
   void *d_S2 = nullptr;           // spectral form: second half spectrum (j_y, then e_y), precision type
   void *d_jcn = nullptr;          // spectral form: per-node jc, NaN off superconducting nodes (precision type)
-  long long jcn_gen = -1;         // set-up generation d_jcn was computed for
+  unsigned long long jcn_gen = 0; // set-up generation d_jcn was computed for (0: none; gen starts at 1)
   long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
   double *d_sym = nullptr;        // per-axis symbol tables (double)
   long long sym_off[8] = {0};

@@ -49,6 +49,55 @@ def test_film_vjp_dot_product_fixed_count(kind, fixed):
     assert abs(lhs - rhs) < 1e-6 * abs(lhs)
 
 
+@pytest.mark.parametrize("kind,fixed,nx,ny", [("offrect", 3, 32, 32), ("ring", 2, 32, 32), ("hole", 2, 48, 32)])
+def test_film_spectral_vjp_dot_product_fixed_count(kind, fixed, nx, ny):
+    """The spectral form (Sec. 2.2): central differences of the forward map in
+    the state and in the jc map against the transposed spectral passes."""
+    L = (2.25, 1.5) if kind == "hole" else (2.0, 2.0)
+    case = film_case(nx, ny, L=L, kind=kind, jc_s=0.2, n=5.0, rho_out=3.0)
+    prob = make_oracle(case, fixed=fixed, deriv="spectral")
+    g = case["state"]
+    rng = np.random.default_rng(13)
+    v = rng.standard_normal(g.shape)
+    w = rng.standard_normal(g.shape)
+    eps = 1e-6
+    Jv = (_f(prob, g + eps * v) - _f(prob, g - eps * v)) / (2 * eps)
+    gbar, jcbar, cnt, st = adjoint.film_rhs_vjp(prob, g, 0.1, w)
+    assert st == 0 and cnt == fixed
+    lhs, rhs = np.vdot(w, Jv), np.vdot(gbar, v)
+    assert abs(lhs - rhs) < 1e-6 * abs(lhs)
+    jc = case["jc"]
+    u = rng.standard_normal(jc.shape)
+
+    def fj(m):
+        c2 = dict(case)
+        c2["jc"] = m
+        return _f(make_oracle(c2, fixed=fixed, deriv="spectral"), g)
+
+    Ju = (fj(jc + eps * u) - fj(jc - eps * u)) / (2 * eps)
+    lhs, rhs = np.vdot(w, Ju), np.vdot(jcbar, u)
+    assert abs(lhs - rhs) < 1e-6 * abs(lhs)
+
+
+def test_film_spectral_vjp_dense_jacobian_ohmic():
+    """n = 1 in the spectral form: f is affine in g, so unit-vector differences
+    give the Jacobian exactly; J^T w must match the VJP."""
+    case = film_case(16, 16, kind="offrect", jc_s=0.3, n=1.0, rho_out=2.0)
+    prob = make_oracle(case, fixed=3, deriv="spectral")
+    g = case["state"]
+    f0 = _f(prob, g)
+    N = g.size
+    J = np.empty((N, N))
+    for i in range(N):
+        e = np.zeros(N)
+        e[i] = 1.0
+        J[:, i] = (_f(prob, g + e.reshape(g.shape)) - f0).ravel()
+    w = np.random.default_rng(4).standard_normal(g.shape)
+    gbar, _, _, _ = adjoint.film_rhs_vjp(prob, g, 0.1, w)
+    ref = (J.T @ w.ravel()).reshape(g.shape)
+    assert np.abs(gbar - ref).max() < 1e-10 * np.abs(ref).max()
+
+
 def test_film_vjp_dense_jacobian_ohmic():
     """n = 1 (Ohm law in the film): f is affine in g, so unit-vector
     differences give the Jacobian exactly; J^T w must match the VJP."""
