@@ -235,7 +235,8 @@ int mag_reset_warm_start(mag_ctx *ctx);
  * the film nodes.  sigma < 0 selects the width of Sec. 2.2, sqrt(dx^2 + dy^2),
  * for the grid in force at each call.  The update (12) stays unfiltered in
  * both forms.  mag_observe then returns j at the nodes (j_x, then j_y, each
- * nx*ny), and mag_rhs_vjp returns MAG_E_STATE (it covers the staggered form).
+ * nx*ny), and mag_rhs_vjp transposes this form (the filtered derivatives are
+ * antisymmetric; the jc cotangent of a node goes to its four cells).
  * May be called before or after mag_set_grid; the spectral form holds two
  * more double arrays of nx*ny on the device.  Drops the warm start. */
 int mag_set_derivatives(mag_ctx *ctx, int mode, double sigma);

@@ -523,14 +523,16 @@ static bool pow2x3_in(int n, int lo, int hi) { return n % 3 == 0 && pow2_in(n / 
 static void free_all(mag_ctx *c) {
   void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
                   c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_w,
-                  c->d_tw64, c->d_it64, c->d_w64, c->d_S2, c->d_jcn};
+                  c->d_tw64, c->d_it64, c->d_w64, c->d_S2, c->d_jcn, c->d_S34, c->d_cn, c->d_itv};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_mat = c->d_flags = nullptr;
   c->d_jc = c->d_H = c->d_G = c->d_S = c->d_box = c->d_tw = c->d_w = c->d_tw64 = nullptr;
   c->d_it64 = nullptr;
   c->d_w64 = nullptr;
-  c->d_S2 = c->d_jcn = nullptr;
+  c->d_S2 = c->d_jcn = c->d_S34 = nullptr;
+  c->d_cn = nullptr;
+  c->d_itv = nullptr;
   c->d_jc64 = c->d_part = c->d_sym = c->d_rk = c->d_red = nullptr;
   c->d_it = nullptr;
   c->nred = 0;

@@ -142,6 +142,9 @@ struct mag_ctx {
   void *d_S2 = nullptr;           // spectral form: second half spectrum (j_y, then e_y), precision type
   void *d_jcn = nullptr;          // spectral form: per-node jc, NaN off superconducting nodes (precision type)
   unsigned long long jcn_gen = 0; // set-up generation d_jcn was computed for (0: none; gen starts at 1)
+  void *d_S34 = nullptr;          // spectral VJP: two more half spectra (j_x, j_y), precision type
+  double *d_cn = nullptr;         // spectral VJP: cotangent of the node jc
+  mag::IterState *d_itv = nullptr;   // spectral VJP: state of its passes (C of the transposed iteration)
   long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
   double *d_sym = nullptr;        // per-axis symbol tables (double)
   long long sym_off[8] = {0};

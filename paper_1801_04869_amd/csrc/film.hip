@@ -343,6 +343,8 @@ __device__ __forceinline__ void row_tw_put(const RowTw<T, M, THREADS> &rt, const
 //         per-block sums pp.in when given, else it->A).
 // MODE 3: rows of the float iterate xf minus dh_e (it->hde), per-block sums
 //         of w1 (xf - dh_e) over all nodes (the final double evaluation).
+// MODE 6: rows of X - it->C on film nodes (flag bit 0), 0 elsewhere (the film
+//         cotangent of the transposed iteration, spectral form).
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_fwd(T *__restrict__ X, const double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -444,6 +446,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           acc += fabs(gd);
           val[e] = (T)gd;
         }
+      } else if constexpr (MODE == 6) {
+        if (flags[ro + p] & 1) val[e] = (T)((double)X[ro + p] - it->C);
       } else if constexpr (MODE == 5) {
         const double y = xd[ro + p] - ((flags[ro + p] & 1) ? 0.0 : shift);
         val[e] = (T)y;
@@ -799,6 +803,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 //         pp.out, sums of |gdot| over free space.
 // Spectral form:
 // MODE 7: write the value into X at film nodes (flag bit 0), nothing else.
+// MODE 8: write -value (double).
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
     film_rows_inv(T *__restrict__ X, double *__restrict__ xd, const uint8_t *__restrict__ flags,
@@ -881,6 +886,8 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
           acc2 += fabs((double)val[e]);
         } else if constexpr (MODE == 7) {
           if (!out) X[ro + p] = val[e];
+        } else if constexpr (MODE == 8) {
+          xd[ro + p] = -(double)val[e];
         } else if constexpr (MODE == 6) {
           const double gd = (double)val[e] - cmean;
           xd[ro + p] = gd;
@@ -891,7 +898,7 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
       }
     }
   }
-  if constexpr (MODE != 2 && MODE != 7) {
+  if constexpr (MODE != 2 && MODE != 7 && MODE != 8) {
     if (MODE != 6 || pp.out) {   // uniform over the block
       const double sblk = block_total<RS::THREADS>(acc, red);
       if (threadIdx.x == 0) pp.out[blk] = sblk;
@@ -1262,6 +1269,150 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
   r2c_store(jy, S2);
 }
 
+// Row pass of the transposed spectral form: C2R of the spectra of j_x (Sj),
+// j_y (Sj2), a = d_y hbar (S) and b = -d_x hbar (S2), so that e_bar =
+// (-a, -b); then at each node j_bar = rho e_bar + rho (n-1) (j.e_bar) j / |j|^2
+// and the cotangent of the node jc, -n rho (j.e_bar) / jc, at power-law nodes
+// (jcn a number), j_bar = rho_out e_bar elsewhere; R2C of j_bar_x (to S) and
+// j_bar_y (to S2); the node jc cotangent to cn (if not null).  The four tiles
+// pass through the LDS one after the other.
+template <typename T, int M>
+__global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
+    MAG_WAVES_PER_EU(FilmRowShape<M, T>::WAVES_EU)
+    film_rows_node_ebar(cx<T> *__restrict__ S, cx<T> *__restrict__ S2, const cx<T> *__restrict__ Sj,
+                        const cx<T> *__restrict__ Sj2, const T *__restrict__ jcn, double *__restrict__ cn,
+                        const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN, FilmGeom G, FilmLaw law,
+                        const IterState *__restrict__ it) {
+  using RS = FilmRowShape<M, T>;
+  using PL = typename RS::PL;
+  constexpr int TT = RS::TT, P = RS::P, RMAX = PL::RMAX, PITCH = RS::PITCH, SP = RS::SP;
+  __shared__ __align__(16) T lds[RS::LDS_T];
+  const int pr = threadIdx.x / TT, j = threadIdx.x % TT;
+  const int blk = xcd_block(blockIdx.x, (G.ny + P - 1) / P);
+  const int q0 = blk * P;
+  const int q = q0 + pr;
+  const bool active = q < G.ny;
+  const long long ro = (long long)(active ? q : 0) * G.nx;
+  cx<T> *tile = reinterpret_cast<cx<T> *>(lds);   // [M+1][SP]
+  RowTw<T, M, RS::THREADS> rtw;
+  row_tw_fetch(rtw, twM, twN);
+  if (it->done) return;
+  T jn[RMAX][2];
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const long long o = ro + 2 * (j + rho * TT);
+    jn[rho][0] = jcn[o];
+    jn[rho][1] = jcn[o + 1];
+  }
+  cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pr * PITCH;
+  auto lidx = [](int i) { return lds_pad<T>(i); };
+  bool tw_ready = false;
+  // C2R of the spectrum Src along the block's rows into vv (nodes 2m, 2m+1)
+  auto c2r = [&](const cx<T> *__restrict__ Src, cx<T> *vv) {
+    TileRegs<T, M, P, RS::THREADS> tr;
+    tile_fetch(tr, Src, G.ny, q0);
+    __syncthreads();   // the previous use of the LDS is done
+    tile_put<T, M, P, SP, RS::THREADS>(tile, tr);
+    if (!tw_ready) row_tw_put(rtw, twM, twN);
+    tw_ready = true;
+    __syncthreads();
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const int k = j + rho * TT;
+      const cx<T> a = tile[k * SP + pr];
+      const cx<T> b = tile[(M - k) * SP + pr];
+      const cx<T> sum = {a.x + b.x, a.y - b.y};
+      const cx<T> dif = {a.x - b.x, a.y + b.y};
+      const cx<T> wd = cmulc(dif, twN[k]);
+      vv[rho] = {sum.x - wd.y, sum.y + wd.x};
+    }
+    if constexpr (PL::S == 1) __syncthreads();
+    pencil_fft_cx<M, +1, PL>(vv, j, xch, lidx, twM);
+  };
+  auto r2c_store = [&](cx<T> *vv, cx<T> *__restrict__ D) {
+    pencil_fft_cx<M, -1, PL>(vv, j, xch, lidx, twM);
+    __syncthreads();
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) xch[j + rho * TT] = vv[rho];
+    __syncthreads();
+    cx<T> xk[RMAX];
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) {
+      const int k = j + rho * TT;
+      const int km = k == 0 ? 0 : M - k;
+      const cx<T> zk = vv[rho];
+      const cx<T> zm = conj(xch[km]);
+      const cx<T> sum = zk + zm, dif = zk - zm;
+      const cx<T> wd = cmul(twN[k], dif);
+      xk[rho] = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
+    }
+    const cx<T> xm = {vv[0].x - vv[0].y, (T)0};
+    __syncthreads();
+#pragma unroll
+    for (int rho = 0; rho < RMAX; ++rho) tile[(j + rho * TT) * SP + pr] = xk[rho];
+    if (j == 0) tile[M * SP + pr] = xm;
+    __syncthreads();
+    tile_store<T, M, P, SP, RS::THREADS>(tile, D, G.ny, q0);
+  };
+  cx<T> jx[RMAX], jy[RMAX], ax[RMAX], ay[RMAX];
+  c2r(Sj, jx);
+  c2r(Sj2, jy);
+  c2r(S, ax);
+  c2r(S2, ay);
+  const T e0 = (T)law.e0, nm1 = (T)law.nm1, lmax = (T)law.lmax, rout = (T)law.rho_out, nex = (T)(law.nm1 + 1.0);
+#pragma unroll
+  for (int rho = 0; rho < RMAX; ++rho) {
+    const T jxv[2] = {jx[rho].x, jx[rho].y}, jyv[2] = {jy[rho].x, jy[rho].y};
+    const T ex[2] = {-ax[rho].x, -ax[rho].y}, ey[2] = {-ay[rho].x, -ay[rho].y};
+    T bx[2], by[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const T jcv = jn[rho][e];
+      T c_node = (T)0;
+      if (isnan(jcv)) {
+        bx[e] = rout * ex[e];
+        by[e] = rout * ey[e];
+      } else {
+        const T s2 = jxv[e] * jxv[e] + jyv[e] * jyv[e];
+        const T r = film_rho(sqrt(s2), jcv, e0, nm1, lmax);
+        const T jd = jxv[e] * ex[e] + jyv[e] * ey[e];
+        const T fac = s2 > (T)0 ? r * nm1 * jd / s2 : (T)0;
+        bx[e] = r * ex[e] + fac * jxv[e];
+        by[e] = r * ey[e] + fac * jyv[e];
+        c_node = -nex * r * jd / jcv;
+      }
+      if (cn && active) cn[ro + 2 * (j + rho * TT) + e] = (double)c_node;
+    }
+    jx[rho] = {bx[0], bx[1]};
+    jy[rho] = {by[0], by[1]};
+  }
+  __syncthreads();   // the last C2R's LDS reads are done
+  r2c_store(jx, S);
+  __syncthreads();
+  r2c_store(jy, S2);
+}
+
+// Cotangent of the cell jc map from that of the node jc (node (p, q) takes
+// the mean of cells (p,q), (p-1,q), (p,q-1), (p-1,q-1)): cell (p, q)
+// collects a quarter of nodes (p,q), (p+1,q), (p,q+1), (p+1,q+1), times jc0.
+__global__ void __launch_bounds__(256) film_cell_jcbar(const double *__restrict__ cn, double *__restrict__ jcbar,
+                                                       FilmGeom G, double scale) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = (long long)G.nx * G.ny;
+  if (i >= n) return;
+  const int p = (int)(i % G.nx), q = (int)(i / G.nx);
+  const long long r0 = (long long)q * G.nx, r1 = (long long)wrap(q + 1, G.ny) * G.nx;
+  const int p1 = wrap(p + 1, G.nx);
+  jcbar[i] = 0.25 * scale * (cn[r0 + p] + cn[r0 + p1] + cn[r1 + p] + cn[r1 + p1]);
+}
+
+__global__ void __launch_bounds__(64) vjp_gate_k(const IterState *__restrict__ it, IterState *__restrict__ gate) {
+  if (threadIdx.x == 0) {
+    *gate = IterState{};
+    gate->C = it->C;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) film_out(const T *__restrict__ Gm, double *__restrict__ out, long long n,
                                                 const IterState *__restrict__ it) {
@@ -1620,7 +1771,7 @@ static Parts parts(const double *in, int nin, double *out, double *out2 = nullpt
 
 template <typename T, int MODE>
 static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, int kid, IterState *its = nullptr,
-                    const float *xf = nullptr) {
+                    const float *xf = nullptr, cx<T> *dst = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   ProfLaunch ps(c, kid);
@@ -1628,7 +1779,7 @@ static int film_fwd(mag_ctx *c, T *X, const double *xd, double hde, Parts pp, in
     using RS = FilmRowShape<MM, T>;
     const int nblk = (G.ny + RS::P - 1) / RS::P;
     MAG_TIMED_LAUNCH(ps, (film_rows_fwd<T, MM, MODE>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, X, xd,
-                       c->d_flags, f.S, f.twM, f.twN, G, hde, pp, its ? its : c->d_it,
+                       c->d_flags, dst ? dst : f.S, f.twM, f.twN, G, hde, pp, its ? its : c->d_it,
                        ((MODE == 0 || MODE == 3 || MODE == 5) && pp.out) ? (const T *)f.w1 : (const T *)nullptr, xf);
   });
   return MAG_OK;
@@ -1696,7 +1847,8 @@ static int film_col(mag_ctx *c, int which, Parts pp = parts(nullptr, 0, nullptr)
 
 // Column pass of the spectral form (OP 0: gradient of g, OP 1: curl of e).
 template <typename T, int OP>
-static int film_col_spec(mag_ctx *c, int kid) {
+static int film_col_spec(mag_ctx *c, int kid, cx<T> *Sa = nullptr, cx<T> *Sb = nullptr,
+                         const IterState *its = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   // the Gaussian width of Sec. 2.2, by default sqrt(dx^2 + dy^2)
@@ -1705,9 +1857,9 @@ static int film_col_spec(mag_ctx *c, int kid) {
   FILM_SWITCH_N(G.ny, {
     using CS = FilmColShape<NN, T>;
     const int nblk = (G.kx - 1 + CS::P - 1) / CS::P;
-    MAG_TIMED_LAUNCH(ps, (film_cols_spec<T, NN, OP>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, f.S,
-                     reinterpret_cast<cx<T> *>(c->d_S2), G.kx, f.k2x, f.k2y, f.kxs, f.kys, 1.0 / (double)c->nnode,
-                     0.5 * sig * sig, f.twY, (const IterState *)c->d_it);
+    MAG_TIMED_LAUNCH(ps, (film_cols_spec<T, NN, OP>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, Sa ? Sa : f.S,
+                     Sb ? Sb : reinterpret_cast<cx<T> *>(c->d_S2), G.kx, f.k2x, f.k2y, f.kxs, f.kys,
+                     1.0 / (double)c->nnode, 0.5 * sig * sig, f.twY, its ? its : (const IterState *)c->d_it);
   });
   return MAG_OK;
 }
@@ -2044,6 +2196,60 @@ int film_hz_transpose(mag_ctx *c, const double *hz_bar, double *state_bar) {
 // (Q^T z = K1 (z - m_out sum_D z), S^T z = z - mean_out z), stopped after the
 // forward's fixed count or when mean_out |nu| < tol mean_D |Q^T ybar|, then
 // the stencil transpose on the film part of S^T mu.
+// Transpose of the spectral form's film values (the film cotangent Mu - C
+// from the transposed iteration) to the state and the jc map.  The passes
+// run under their own iteration state (the transposed iteration's is done).
+template <typename T>
+static int film_spectral_vjp(mag_ctx *c, const double *state, const T *Mu, double *gbar, double *jcbar) {
+  const FilmGeom G = fgeom(c);
+  const FilmPtrs<T> f = fptrs<T>(c);
+  const FilmLaw law = film_law(c);
+  const size_t ts = sizeof(T);
+  if (!c->d_S2 || !c->d_jcn) return set_error(c, MAG_E_STATE, "spectral form without its buffers");
+  if (!c->d_S34) MAG_HIP(c, hipMalloc(&c->d_S34, 2 * c->nspec * 2 * ts));
+  if (!c->d_cn) MAG_HIP(c, hipMalloc(&c->d_cn, c->nnode * sizeof(double)));
+  if (!c->d_itv) MAG_HIP(c, hipMalloc(&c->d_itv, sizeof(IterState)));
+  cx<T> *S = f.S, *S2 = reinterpret_cast<cx<T> *>(c->d_S2);
+  cx<T> *S3 = reinterpret_cast<cx<T> *>(c->d_S34), *S4 = S3 + c->nspec;
+  IterState *gate = c->d_itv;
+  {
+    ProfScope ps(c, K_VJP);
+    hipLaunchKernelGGL(vjp_gate_k, dim3(1), dim3(64), 0, c->stream, (const IterState *)c->d_it, gate);
+    if (c->jcn_gen != c->gen) {
+      hipLaunchKernelGGL((film_node_jc<T>), dim3((unsigned)((c->nnode + 255) / 256)), dim3(256), 0, c->stream,
+                         c->d_mat, reinterpret_cast<const T *>(c->d_jc), reinterpret_cast<T *>(c->d_jcn), G, law);
+      c->jcn_gen = c->gen;
+    }
+  }
+  int rc;
+  // the spectra of j_x, j_y (from g) to S3, S4
+  if ((rc = film_fwd<T, 2>(c, nullptr, state, 0.0, parts(nullptr, 0, nullptr), K_VJP, gate, nullptr, S3))) return rc;
+  if ((rc = film_col_spec<T, 0>(c, K_VJP, S3, S4, gate))) return rc;
+  // the spectra of d_y hbar, -d_x hbar (hbar = Mu - C on the film) to S, S2
+  if ((rc = film_fwd<T, 6>(c, const_cast<T *>(Mu), nullptr, 0.0, parts(nullptr, 0, nullptr), K_VJP, gate))) return rc;
+  if ((rc = film_col_spec<T, 0>(c, K_VJP, S, S2, gate))) return rc;
+  {
+    ProfLaunch ps(c, K_VJP);
+    FILM_SWITCH_M(G.nx / 2, {
+      using RS = FilmRowShape<MM, T>;
+      const int nblk = (G.ny + RS::P - 1) / RS::P;
+      MAG_TIMED_LAUNCH(ps, (film_rows_node_ebar<T, MM>), dim3(nblk), dim3(RS::THREADS), 0, c->stream, S, S2,
+                       (const cx<T> *)S3, (const cx<T> *)S4, reinterpret_cast<const T *>(c->d_jcn),
+                       jcbar ? c->d_cn : nullptr, f.twM, f.twN, G, law, (const IterState *)gate);
+    });
+  }
+  // g_bar = -(d_y jbar_x - d_x jbar_y)
+  if ((rc = film_col_spec<T, 1>(c, K_VJP, S, S2, gate))) return rc;
+  if ((rc = film_inv<T, 8>(c, nullptr, gbar, 0.0, parts(nullptr, 0, nullptr), K_VJP, gate))) return rc;
+  if (jcbar) {
+    ProfScope ps(c, K_VJP);
+    hipLaunchKernelGGL(film_cell_jcbar, dim3((unsigned)((c->nnode + 255) / 256)), dim3(256), 0, c->stream,
+                       (const double *)c->d_cn, jcbar, G, c->jc0);
+  }
+  MAG_HIP(c, hipGetLastError());
+  return MAG_OK;
+}
+
 template <typename T>
 static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, double *gbar, double *jcbar) {
   const FilmGeom G = fgeom(c);
@@ -2124,6 +2330,7 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
   law.lmax = std::log(1e30) / (c->nexp - 1.0 > 1e-12 ? c->nexp - 1.0 : 1e-12);
   law.jc0 = c->jc0;
   law.has_jc = c->has_jc_map ? 1 : 0;
+  if (c->deriv == 1) return film_spectral_vjp<T>(c, state, Mu, gbar, jcbar);
   {
     ProfLaunch ps(c, K_VJP);
     MAG_TIMED_LAUNCH(ps, (film_vjp_stencil<T>), dim3(G.nx / kVjpTile, G.ny / kVjpTile), dim3(kVjpTile * kVjpTile),
@@ -2136,7 +2343,6 @@ static int film_rhs_vjp_t(mag_ctx *c, const double *state, const double *ybar, d
 
 int film_rhs_vjp(mag_ctx *c, const double *state, double, const double *out_bar, double *state_bar,
                  double *jc_bar) {
-  if (c->deriv != 0) return set_error(c, MAG_E_STATE, "the VJP covers the staggered differences only");
   return c->prec == MAG_FP64 ? film_rhs_vjp_t<double>(c, state, out_bar, state_bar, jc_bar)
                              : film_rhs_vjp_t<float>(c, state, out_bar, state_bar, jc_bar);
 }

@@ -1,4 +1,4 @@
-"""End-to-end check of the film path against the Bean model (Sec. 3, first
+"""End-to-end check of the film path against the Bean model (Sec. 2.3, first
 example): a thin disk of radius 1 in [-2, 2]^2, power law n = 1000 (close to
 the Bean critical state), rho_out = 1, field ramp h_e = t, integrated on the
 GPU with the adaptive driver from the virgin state to h_e = 0.5.  The sheet

@@ -136,13 +136,27 @@ def test_spectral_observables(prec):
     assert abs(m[2] - rmz) <= 1e-12 * abs(rmz)
 
 
-def test_spectral_vjp_is_refused():
-    case = film_case(64, 64, L=(1.0, 1.0), kind="disk")
-    ctx = make_gpu(case, api.FP64, fixed=2, deriv=SP)
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+@pytest.mark.parametrize("fixed", [2, 0])
+def test_spectral_vjp(prec, fixed):
+    """mag_rhs_vjp in the spectral form against the oracle's transpose
+    (fixed count and converged), for the state and the jc map."""
+    from oracle import adjoint
+    case = film_case(128, 64, L=(2.0, 1.0), kind="offrect", jc_s=0.2, n=19.0, rho_out=5.0)
+    ctx = make_gpu(case, prec, fixed=fixed, deriv=SP)
+    prob = make_oracle(case, fixed=fixed, deriv=SP)
+    ybar = np.random.default_rng(17).standard_normal(case["state"].shape)
     s = torch.from_numpy(case["state"]).cuda()
-    with pytest.raises(api.MagError) as e:
-        ctx.rhs_vjp(s, 0.2, torch.ones_like(s), torch.empty_like(s))
-    assert e.value.code == api.E_STATE
+    yb = torch.from_numpy(ybar).cuda()
+    gb, jb = torch.empty_like(s), torch.empty_like(s)
+    rc = ctx.rhs_vjp(s, 0.2, yb, gb, jb)
+    rg, rj, rcnt, rst = adjoint.film_rhs_vjp(prob, case["state"], 0.2, ybar)
+    e1, e2 = rel_l2(gb.cpu().numpy(), rg), rel_l2(jb.cpu().numpy(), rj)
+    print("spectral VJP precision %d fixed %d: rel-L2 g %.3e jc %.3e (oracle count %d)" % (prec, fixed, e1, e2, rcnt),
+          flush=True)
+    assert rc == api.OK and rst == 0
+    tol = TOL[prec] if (fixed or prec == api.FP64) else 10 * prob.tol
+    assert e1 < tol and e2 < tol
 
 
 def test_spectral_form_switches_back():
@@ -158,7 +172,7 @@ def test_spectral_form_switches_back():
 
 
 def test_spectral_disk_current_matches_bean_model():
-    """Sec. 3, first example, in the paper's own discretisation: a disk of
+    """Sec. 2.3, first example, in the paper's own discretisation: a disk of
     radius 1 in [-2, 2]^2 on a 128^2 grid, n = 1000, rho_out = 1, h_e = t,
     integrated from the virgin state to h_e = 0.5 with the adaptive driver.
     |j| at the nodes inside the disk is compared with the Bean solution
