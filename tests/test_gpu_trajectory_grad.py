@@ -120,3 +120,27 @@ def test_hz_misfit_gradient():
             bars[i] = adjoint.film_hz_vjp(prob, (hz_o - obs[i]) * dA)
     _, jb_ref, _ = adjoint.film_trajectory_grad(prob, g0, 0.1, steps, bars)
     assert rel_l2(jc_t.grad.cpu().numpy(), jb_ref) < 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.MIXED, 1e-4)])
+def test_checkpointed_trajectory_gradient_spectral(prec, tol):
+    """The same loss and checkpointing (every 2 steps) in the spectral form of
+    Sec. 2.2: gradients of g0 and the jc map against the oracle's."""
+    case = _case()
+    ctx = make_gpu(case, prec, fixed=3, deriv="spectral")
+    prob = make_oracle(case, fixed=3, deriv="spectral")
+    g0 = case["state"]
+    steps = [2e-3, 3e-3, 1.5e-3, 2.5e-3, 2e-3]
+    rng = np.random.default_rng(9)
+    w1, w4 = rng.standard_normal(g0.shape), rng.standard_normal(g0.shape)
+    gb_ref, jb_ref, yend = adjoint.film_trajectory_grad(prob, g0, 0.1, steps, [None, w1, None, None, w4])
+    g0_t = torch.from_numpy(g0).cuda().requires_grad_(True)
+    jc_t = torch.from_numpy(case["jc"]).cuda().requires_grad_(True)
+    y1, y4 = ag.trajectory(ctx, g0_t, jc_t, 0.1, steps, [1, 4], every=2)
+    loss = (torch.from_numpy(w1).cuda() * y1).sum() + (torch.from_numpy(w4).cuda() * y4).sum()
+    loss.backward()
+    e0 = rel_l2(y4.detach().cpu().numpy(), yend)
+    e1 = rel_l2(g0_t.grad.cpu().numpy(), gb_ref)
+    e2 = rel_l2(jc_t.grad.cpu().numpy(), jb_ref)
+    print("spectral, precision %d: state %.3e, grad rel-L2 g0 %.3e jc %.3e" % (prec, e0, e1, e2), flush=True)
+    assert e0 < tol and e1 < tol and e2 < tol
