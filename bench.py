@@ -341,11 +341,22 @@ def spectral_run(prec, wl, mat, jc, g, steps, warmup, t, fixed, lam):
     loop(steps)
     prof = ctx.prof_read()
     ctx.prof_enable(False)
+    # the VJP of the same right-hand side (the transposed spectral passes)
+    ybar = torch.ones_like(state)
+    gbar, jcbar = torch.empty_like(state), torch.empty_like(state)
+    for _ in range(warmup):
+        assert ctx.rhs_vjp(state, t, ybar, gbar, jcbar) == 0, ctx.last_error()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        assert ctx.rhs_vjp(state, t, ybar, gbar, jcbar) == 0, ctx.last_error()
+    torch.cuda.synchronize()
+    dt_vjp = time.perf_counter() - t2
     ctx.close()
     per_rhs = {k: dict(launches_per_rhs=round(c / steps, 2), us_per_rhs=round(1e3 * ms / steps, 2),
                        avg_us=round(1e3 * ms / c, 2)) for k, (c, ms) in prof.items()}
     return dict(value=round(steps / dt, 3), unit="RHS evals/s", ms_per_step=round(1e3 * dt / steps, 4),
-                kernels=per_rhs)
+                adjoint_forward_ratio=round(dt_vjp / dt, 3), kernels=per_rhs)
 
 
 def hole_film_lines(a):
