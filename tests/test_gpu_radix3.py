@@ -194,3 +194,19 @@ def test_grid_sizes_accepted_and_refused():
     with pytest.raises(api.MagError):
         c.set_grid(48, 48, 48, 1.0, 1.0, 1.0)
     c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+def test_radix3_largest_grid(form, prec):
+    """768 x 768 nodes (the largest grid of 3 * 2^k nodes on both axes), the
+    hole film geometry, 3 inner iterations, every node against the oracle."""
+    case = film_case(768, 768, L=(2.25, 2.25), kind="hole", jc_s=0.2, n=30.0, rho_out=50.0)
+    ctx = make_gpu(case, prec, lam=0.4, fixed=3, deriv=form)
+    prob = make_oracle(case, lam=0.4, fixed=3, deriv=form)
+    st, it, out = _gpu_rhs(ctx, case["state"], 0.2)
+    ref, rit, rst = film.rhs(prob, case["state"], 0.2)
+    e = rel_l2(out, ref)
+    print("768^2 %s precision %d: rel-L2 %.3e" % (form, prec, e), flush=True)
+    assert st == 0 and rst == 0 and it == rit == 3
+    assert e < TOL[prec]

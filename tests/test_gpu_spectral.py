@@ -244,3 +244,26 @@ def test_spectral_integration_matches_oracle():
     err = rel_l2(y.cpu().numpy().ravel(), yo)
     print("captured %d accepted, oracle %d; rel-L2 %.3e" % (na, len(hist), err), flush=True)
     assert abs(na - len(hist)) <= 2 and err < 1e-5
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.MIXED])
+def test_spectral_2048_vjp_matches_oracle(prec):
+    """The 2048^2 ring workload (4 iterations) in the spectral form: the
+    whole-field VJP for the state and the jc map against the oracle."""
+    import bench
+    from oracle import adjoint
+    from oracle.field import AppliedField
+    wl, mat, jc, g = bench.film_inputs("ring", 0.6)
+    ctx = bench.make_ctx("mixed" if prec == api.MIXED else "fp64", wl, mat, jc, fixed=4, lam=0.4, deriv=SP)
+    ybar = np.random.default_rng(6).standard_normal(g.shape)
+    s = torch.from_numpy(g).cuda()
+    gb, jb = torch.empty_like(s), torch.empty_like(s)
+    assert ctx.rhs_vjp(s, 0.6, torch.from_numpy(ybar).cuda(), gb, jb) == api.OK
+    f = wl["field"]
+    prob = film.FilmProblem(2048, 2048, *wl["L"], mat, jc_cell=jc, n=wl["nexp"], rho_out=wl["rho_out"], lam=0.4,
+                            tol=2e-4, max_inner=4, fixed_iters=4, deriv=SP,
+                            field=AppliedField(f["kind"], f["dir"], f["amp"], f["omega"], f["rate"]))
+    rg, rj, cnt, rst = adjoint.film_rhs_vjp(prob, g, 0.6, ybar)
+    e1, e2 = rel_l2(gb.cpu().numpy(), rg), rel_l2(jb.cpu().numpy(), rj)
+    print("spectral 2048^2 VJP precision %d: rel-L2 g %.3e jc %.3e" % (prec, e1, e2), flush=True)
+    assert rst == 0 and e1 < TOL[prec] and e2 < TOL[prec]
