@@ -237,8 +237,9 @@ int mag_reset_warm_start(mag_ctx *ctx);
  * both forms.  mag_observe then returns j at the nodes (j_x, then j_y, each
  * nx*ny), and mag_rhs_vjp transposes this form (the filtered derivatives are
  * antisymmetric; the jc cotangent of a node goes to its four cells).
- * May be called before or after mag_set_grid; the spectral form holds two
- * more double arrays of nx*ny on the device.  Drops the warm start. */
+ * May be called before or after mag_set_grid; the spectral form holds three
+ * more half spectra and two more node arrays on the device (allocated here or
+ * by mag_set_grid, not by mag_rhs or mag_rhs_vjp).  Drops the warm start. */
 int mag_set_derivatives(mag_ctx *ctx, int mode, double sigma);
 
 /* on = 0: every right-hand side starts the free-space iteration from dh_e/dt

@@ -836,11 +836,8 @@ int mag_set_derivatives(mag_ctx *c, int mode, double sigma) {
   if (!std::isfinite(sigma)) return set_error(c, MAG_E_ARG, "sigma must be finite");
   ++c->gen;   // a captured step graph bakes the set-up in
   MAG_HIP(c, hipStreamSynchronize(c->stream));
-  if (mode == MAG_DERIV_SPECTRAL && c->grid_set && !c->d_S2) {
-    const size_t ts = c->prec == MAG_FP64 ? 8 : 4;
-    MAG_HIP(c, hipMalloc(&c->d_S2, c->nspec * 2 * ts));
-    MAG_HIP(c, hipMalloc(&c->d_jcn, c->nnode * ts));
-  }
+  if (mode == MAG_DERIV_SPECTRAL && c->grid_set)
+    if (int rc = film_spectral_alloc(c)) return rc;
   c->deriv = mode;
   c->dsigma = sigma;
   c->warm_valid = false;

@@ -235,6 +235,7 @@ struct ProfLaunch {
 
 // dimension-specific drivers
 int film_alloc(mag_ctx *c);
+int film_spectral_alloc(mag_ctx *c);   // the spectral form's buffers (forward and VJP), if not there yet
 int film_domain(mag_ctx *c);
 int film_rhs(mag_ctx *c, const double *state, double t, double *out, int *n_inner);
 int film_observe(mag_ctx *c, const double *state, double t, double *hz, double *j, double *m);

@@ -2204,11 +2204,8 @@ static int film_spectral_vjp(mag_ctx *c, const double *state, const T *Mu, doubl
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
   const FilmLaw law = film_law(c);
-  const size_t ts = sizeof(T);
-  if (!c->d_S2 || !c->d_jcn) return set_error(c, MAG_E_STATE, "spectral form without its buffers");
-  if (!c->d_S34) MAG_HIP(c, hipMalloc(&c->d_S34, 2 * c->nspec * 2 * ts));
-  if (!c->d_cn) MAG_HIP(c, hipMalloc(&c->d_cn, c->nnode * sizeof(double)));
-  if (!c->d_itv) MAG_HIP(c, hipMalloc(&c->d_itv, sizeof(IterState)));
+  if (!c->d_S2 || !c->d_jcn || !c->d_S34 || !c->d_cn || !c->d_itv)
+    return set_error(c, MAG_E_STATE, "spectral form without its buffers");
   cx<T> *S = f.S, *S2 = reinterpret_cast<cx<T> *>(c->d_S2);
   cx<T> *S3 = reinterpret_cast<cx<T> *>(c->d_S34), *S4 = S3 + c->nspec;
   IterState *gate = c->d_itv;
@@ -2348,6 +2345,21 @@ int film_rhs_vjp(mag_ctx *c, const double *state, double, const double *out_bar,
 }
 
 // ------------------------------------------------------------------ setup
+// The spectral form's buffers: a second half spectrum and the per-node jc
+// (forward); two more half spectra, the node jc cotangent and an iteration
+// state (VJP).  Allocated with the grid or when the form is chosen, never
+// inside a right-hand side or a VJP.
+int film_spectral_alloc(mag_ctx *c) {
+  const size_t ts = c->prec == MAG_FP64 ? 8 : 4;
+  const long long n = c->nnode;
+  if (!c->d_S2) MAG_HIP(c, hipMalloc(&c->d_S2, c->nspec * 2 * ts));
+  if (!c->d_jcn) MAG_HIP(c, hipMalloc(&c->d_jcn, n * ts));
+  if (!c->d_S34) MAG_HIP(c, hipMalloc(&c->d_S34, 2 * c->nspec * 2 * ts));
+  if (!c->d_cn) MAG_HIP(c, hipMalloc(&c->d_cn, n * sizeof(double)));
+  if (!c->d_itv) MAG_HIP(c, hipMalloc(&c->d_itv, sizeof(IterState)));
+  return MAG_OK;
+}
+
 int film_alloc(mag_ctx *c) {
   const size_t ts = c->prec == MAG_FP64 ? 8 : 4;
   const long long n = c->nnode;
@@ -2364,10 +2376,8 @@ int film_alloc(mag_ctx *c) {
   MAG_HIP(c, hipMalloc(&c->d_w, 3 * n * ts));
   MAG_HIP(c, hipMemsetAsync(c->d_H, 0, n * ts, c->stream));
   MAG_HIP(c, hipMemsetAsync(c->d_G, 0, n * ts, c->stream));
-  if (c->deriv == 1) {
-    MAG_HIP(c, hipMalloc(&c->d_S2, c->nspec * 2 * ts));
-    MAG_HIP(c, hipMalloc(&c->d_jcn, n * ts));
-  }
+  if (c->deriv == 1)
+    if (int rc = film_spectral_alloc(c)) return rc;
   if (c->prec == MAG_MIXED_FINAL64) {
     MAG_HIP(c, hipMalloc(&c->d_it64, sizeof(IterState)));
     MAG_HIP(c, hipMemsetAsync(c->d_it64, 0, sizeof(IterState), c->stream));
