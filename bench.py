@@ -456,15 +456,16 @@ def paper_runs():
     mat = W.film_rect_hole(*wl["n"], *wl["L"], h["ax"], h["ay"], h["cx"], h["cy"], h["r"])
     hole = {}
     states = {}
-    for name, prec in (("fp64", api.FP64), ("mixed", api.MIXED)):
+    for name, prec in (("fp64", api.FP64), ("mixed", api.MIXED), ("final64", api.MIXED_FINAL64)):
         g, j, r = run(mat, wl["n"], wl["L"], wl["nexp"], wl["rho_out"], wl["lam"], prec, 0.4)
         states[name] = g.cpu().numpy()
         r.update(lambda_=wl["lam"], paper_wall_min=63.0)
         hole[name] = r
         print("[bench] hole film 768x512 to t = 0.4, %s: %.2f s, %d steps (paper 63 min)" %
               (name, r["wall_s"], r["steps"]), file=sys.stderr, flush=True)
-    hole["mixed_vs_fp64_g_rel_l2"] = float(np.linalg.norm(states["mixed"] - states["fp64"]) /
-                                           np.linalg.norm(states["fp64"]))
+    for name in ("mixed", "final64"):
+        hole["%s_vs_fp64_g_rel_l2" % name] = float(np.linalg.norm(states[name] - states["fp64"]) /
+                                                  np.linalg.norm(states["fp64"]))
     out["hole_film_768x512_t04"] = hole
     return out
 

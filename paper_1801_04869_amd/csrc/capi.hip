@@ -523,7 +523,8 @@ static bool pow2x3_in(int n, int lo, int hi) { return n % 3 == 0 && pow2_in(n / 
 static void free_all(mag_ctx *c) {
   void *ptrs[] = {c->d_mat, c->d_flags, c->d_jc, c->d_jc64, c->d_H, c->d_G, c->d_S, c->d_box,
                   c->d_part, c->d_it, c->d_tw, c->d_sym, c->d_rk, c->d_red, c->d_w,
-                  c->d_tw64, c->d_it64, c->d_w64, c->d_S2, c->d_jcn, c->d_S34, c->d_cn, c->d_itv};
+                  c->d_tw64, c->d_it64, c->d_w64, c->d_S2, c->d_jcn, c->d_S34, c->d_cn, c->d_itv,
+                  c->d_filt};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_mat = c->d_flags = nullptr;
@@ -531,7 +532,7 @@ static void free_all(mag_ctx *c) {
   c->d_it64 = nullptr;
   c->d_w64 = nullptr;
   c->d_S2 = c->d_jcn = c->d_S34 = nullptr;
-  c->d_cn = nullptr;
+  c->d_cn = c->d_filt = nullptr;
   c->d_itv = nullptr;
   c->d_jc64 = c->d_part = c->d_sym = c->d_rk = c->d_red = nullptr;
   c->d_it = nullptr;
@@ -836,12 +837,14 @@ int mag_set_derivatives(mag_ctx *c, int mode, double sigma) {
   if (!std::isfinite(sigma)) return set_error(c, MAG_E_ARG, "sigma must be finite");
   ++c->gen;   // a captured step graph bakes the set-up in
   MAG_HIP(c, hipStreamSynchronize(c->stream));
-  if (mode == MAG_DERIV_SPECTRAL && c->grid_set)
-    if (int rc = film_spectral_alloc(c)) return rc;
   c->deriv = mode;
   c->dsigma = sigma;
   c->warm_valid = false;
   c->fsal_valid = false;
+  // buffers and the filter tables of this sigma (the grid's set-up does the
+  // same when it comes later)
+  if (mode == MAG_DERIV_SPECTRAL && c->grid_set)
+    if (int rc = film_spectral_alloc(c)) return rc;
   return MAG_OK;
 }
 

@@ -145,6 +145,7 @@ struct mag_ctx {
   void *d_S34 = nullptr;          // spectral VJP: two more half spectra (j_x, j_y), precision type
   double *d_cn = nullptr;         // spectral VJP: cotangent of the node jc
   mag::IterState *d_itv = nullptr;   // spectral VJP: state of its passes (C of the transposed iteration)
+  double *d_filt = nullptr;       // spectral form: Gaussian factor per axis (kx entries, then ny)
   long long tw_off[4] = {0, 0, 0, 0};   // offsets: x half-length, y, z, x full-length (R2C post)
   double *d_sym = nullptr;        // per-axis symbol tables (double)
   long long sym_off[8] = {0};

@@ -1021,8 +1021,8 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
 // the symbol i s_a, s_a = k_a exp(-|k|^2 sigma^2 / 2) / N (N = nx ny, the
 // normalisation of the two transforms), with k_a the signed wavenumber of
 // axis a and its Nyquist value set to 0 (an odd symbol has no real value
-// there): kxs, kys; k2x, k2y the full squares for the filter; gs =
-// sigma^2 / 2.  The symbols are Hermitian, so the packed kx = 0 / kx = M
+// there): kxs, kys.  The Gaussian factor is separable: fx[kx] fy[ky] with
+// fx = exp(-kx^2 sigma^2 / 2), fy = exp(-ky^2 sigma^2 / 2) from tables.  The symbols are Hermitian, so the packed kx = 0 / kx = M
 // pencil is split by the identity of film_cols with complex multipliers,
 //   W[k] = (m0 + mM)/2 Zh[k] + (m0 - mM)/2 conj Zh[-k].
 // OP 0 (gradient): from the spectrum of g in S, the spectra of j_x = d_y g
@@ -1031,16 +1031,17 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
 //      dh_z/dt = d_y e_x - d_x e_y (to S), eq. (9).
 template <typename T, int NY, int OP>
 __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
-    film_cols_spec(cx<T> *__restrict__ S, cx<T> *__restrict__ S2, int kx, const double *__restrict__ k2x,
-                   const double *__restrict__ k2y, const double *__restrict__ kxs, const double *__restrict__ kys,
-                   double inv_n, double gs, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
+    film_cols_spec(cx<T> *__restrict__ S, cx<T> *__restrict__ S2, int kx, const double *__restrict__ fx,
+                   const double *__restrict__ fy, const double *__restrict__ kxs, const double *__restrict__ kys,
+                   double inv_n, const cx<T> *__restrict__ tw, const IterState *__restrict__ it) {
   using CS = FilmColShape<NY, T>;
   using PL = typename CS::PL;
   constexpr int TT = CS::TT, P = CS::P, RMAX = PL::RMAX, PITCH = CS::PITCH;
   __shared__ __align__(16) T lds[CS::LDS_T];
   const int pcol = threadIdx.x / TT, j = threadIdx.x % TT;
-  // OP 1 holds two transformed columns: twiddle powers formed per stage
-  TwPre<PL, T, (sizeof(T) > 4 || OP == 1)> twp;
+  // two columns held at once (OP 0: the two results, OP 1: the two inputs):
+  // twiddle powers formed per stage, which keeps 4 waves per SIMD in FP32
+  TwPre<PL, T, true> twp;
   tw_preload<NY, PL>(twp, j, tw);
   const int col = blockIdx.x * P + pcol;
   const bool active = col < kx - 1;
@@ -1059,13 +1060,13 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
       else u[rho] = active ? S2[co + y] : cx<T>{(T)0, (T)0};
     }
   }
-  T ky2[RMAX], kya[RMAX];
+  T fyv[RMAX], kya[RMAX];
 #pragma unroll
   for (int rho = 0; rho < RMAX; ++rho) {
-    ky2[rho] = (T)k2y[j + rho * TT];
+    fyv[rho] = (T)fy[j + rho * TT];
     kya[rho] = (T)kys[j + rho * TT];
   }
-  const T kxx = (T)k2x[active ? col : 0], kxm = (T)k2x[kx - 1];
+  const T fxc = (T)(fx[active ? col : 0] * inv_n), fxm = (T)(fx[kx - 1] * inv_n);
   const T kxa = (T)kxs[active ? col : 0], kxam = (T)kxs[kx - 1];
   if (it->done) return;
   cx<T> *xch = reinterpret_cast<cx<T> *>(lds) + pcol * PITCH;
@@ -1083,7 +1084,6 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
       lds_barrier();
     }
   };
-  const T tgs = (T)gs, tn = (T)inv_n;
   // i (hp Z + hm conj Z[-k]) with hp = (s0 + sM) / 2, hm = (s0 - sM) / 2; i s0 Z off the packed pencil
   auto apply = [&](const cx<T> &z, int k, T s0, T sm) -> cx<T> {
     if (packed) {
@@ -1093,10 +1093,10 @@ __global__ void __launch_bounds__((FilmColShape<NY, T>::THREADS))
     }
     return {-s0 * z.y, s0 * z.x};
   };
-  // the filter at (kx, ky) and, on the packed pencil, at (M, ky)
+  // the filter (times 1/N) at (kx, ky) and, on the packed pencil, at (M, ky)
   auto filt = [&](int rho, T &f0, T &fm) {
-    f0 = exp(-tgs * (kxx + ky2[rho])) * tn;
-    fm = packed ? exp(-tgs * (kxm + ky2[rho])) * tn : (T)0;
+    f0 = fxc * fyv[rho];
+    fm = fxm * fyv[rho];
   };
   mirror_to_lds(v);
 #pragma unroll
@@ -1276,9 +1276,12 @@ __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
 // (jcn a number), j_bar = rho_out e_bar elsewhere; R2C of j_bar_x (to S) and
 // j_bar_y (to S2); the node jc cotangent to cn (if not null).  The four tiles
 // pass through the LDS one after the other.
+// (Four transformed rows are held at once: a register budget of 2 waves per
+// SIMD in FP32 with eight values per work-item, 1 otherwise, so that nothing
+// spills.)
 template <typename T, int M>
 __global__ void __launch_bounds__((FilmRowShape<M, T>::THREADS))
-    MAG_WAVES_PER_EU(FilmRowShape<M, T>::WAVES_EU)
+    MAG_WAVES_PER_EU(sizeof(T) == 4 && FilmRowShape<M, T>::PL::RMAX <= 8 ? 2 : 1)
     film_rows_node_ebar(cx<T> *__restrict__ S, cx<T> *__restrict__ S2, const cx<T> *__restrict__ Sj,
                         const cx<T> *__restrict__ Sj2, const T *__restrict__ jcn, double *__restrict__ cn,
                         const cx<T> *__restrict__ twM, const cx<T> *__restrict__ twN, FilmGeom G, FilmLaw law,
@@ -1851,15 +1854,15 @@ static int film_col_spec(mag_ctx *c, int kid, cx<T> *Sa = nullptr, cx<T> *Sb = n
                          const IterState *its = nullptr) {
   const FilmGeom G = fgeom(c);
   const FilmPtrs<T> f = fptrs<T>(c);
-  // the Gaussian width of Sec. 2.2, by default sqrt(dx^2 + dy^2)
-  const double sig = c->dsigma < 0 ? std::hypot(c->d[0], c->d[1]) : c->dsigma;
+  if (!c->d_filt) return set_error(c, MAG_E_STATE, "spectral form without its filter tables");
   ProfLaunch ps(c, kid);
   FILM_SWITCH_N(G.ny, {
     using CS = FilmColShape<NN, T>;
     const int nblk = (G.kx - 1 + CS::P - 1) / CS::P;
     MAG_TIMED_LAUNCH(ps, (film_cols_spec<T, NN, OP>), dim3(nblk), dim3(CS::THREADS), 0, c->stream, Sa ? Sa : f.S,
-                     Sb ? Sb : reinterpret_cast<cx<T> *>(c->d_S2), G.kx, f.k2x, f.k2y, f.kxs, f.kys,
-                     1.0 / (double)c->nnode, 0.5 * sig * sig, f.twY, its ? its : (const IterState *)c->d_it);
+                     Sb ? Sb : reinterpret_cast<cx<T> *>(c->d_S2), G.kx, (const double *)c->d_filt,
+                     (const double *)c->d_filt + G.kx, f.kxs, f.kys, 1.0 / (double)c->nnode, f.twY,
+                     its ? its : (const IterState *)c->d_it);
   });
   return MAG_OK;
 }
@@ -2357,6 +2360,22 @@ int film_spectral_alloc(mag_ctx *c) {
   if (!c->d_S34) MAG_HIP(c, hipMalloc(&c->d_S34, 2 * c->nspec * 2 * ts));
   if (!c->d_cn) MAG_HIP(c, hipMalloc(&c->d_cn, n * sizeof(double)));
   if (!c->d_itv) MAG_HIP(c, hipMalloc(&c->d_itv, sizeof(IterState)));
+  // the Gaussian factors per axis, exp(-k^2 sigma^2 / 2) over the half
+  // spectrum in x and the full spectrum in y, sigma by default sqrt(dx^2 + dy^2)
+  // (Sec. 2.2); refilled whenever the grid or sigma changes
+  const double sig = c->dsigma < 0 ? std::hypot(c->d[0], c->d[1]) : c->dsigma;
+  const int nx = c->n[0], ny = c->n[1];
+  std::vector<double> tab;
+  for (int m = 0; m < c->kx; ++m) {
+    const double k = 2.0 * M_PI * (double)m / (nx * c->d[0]);
+    tab.push_back(std::exp(-0.5 * sig * sig * k * k));
+  }
+  for (int m = 0; m < ny; ++m) {
+    const double k = 2.0 * M_PI * (double)(m < (ny + 1) / 2 ? m : m - ny) / (ny * c->d[1]);
+    tab.push_back(std::exp(-0.5 * sig * sig * k * k));
+  }
+  if (!c->d_filt) MAG_HIP(c, hipMalloc(&c->d_filt, tab.size() * sizeof(double)));
+  MAG_HIP(c, hipMemcpy(c->d_filt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
   return MAG_OK;
 }
 
