@@ -61,7 +61,7 @@ def make_gpu(case, precision=0, lam=0.7, tol=None, max_inner=100, fixed=0, deriv
     return c
 
 
-def make_oracle(case, lam=0.7, tol=None, max_inner=100, fixed=0, deriv="staggered"):
+def make_oracle(case, lam=0.7, tol=None, max_inner=100, fixed=0, deriv="staggered", deriv_sigma=None):
     from oracle import bulk, film
     from oracle.field import AppliedField
     f = case["field"]
@@ -71,7 +71,7 @@ def make_oracle(case, lam=0.7, tol=None, max_inner=100, fixed=0, deriv="staggere
         return film.FilmProblem(nx, ny, case["L"][0], case["L"][1], case["mat"], jc_cell=case["jc"],
                                 n=case["nexp"], rho_out=case["rho_out"], lam=lam,
                                 tol=2e-4 if tol is None else tol, max_inner=max_inner, fixed_iters=fixed,
-                                field=fld, deriv=deriv)
+                                field=fld, deriv=deriv, deriv_sigma=deriv_sigma)
     return bulk.BulkProblem(nx, ny, nz, *case["L"], case["mat"], jc_cell=case["jc"], n=case["nexp"],
                             rho_out=case["rho_out"], tol=1e-4 if tol is None else tol, max_inner=max_inner,
                             fixed_iters=fixed, field=fld)
