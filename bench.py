@@ -740,6 +740,15 @@ def main():
         workload=film_workload + "; spectral form of Sec. 2.2 (j, e and dh_z/dt on the nodes from filtered "
                                  "Fourier derivatives, sigma = sqrt(dx^2 + dy^2))",
         fixed=sp_lines, converged=sp_conv)
+    # in this form MAG_MIXED itself stays within 1e-4 of FP64 per result along
+    # a converged trajectory (tests/test_gpu_mixed_accuracy.py): its speed-up at
+    # equal accuracy
+    if "mixed" in sp_lines and "fp64" in sp_lines:
+        line["film_2048_spectral"]["mixed_over_fp64_fixed"] = round(sp_lines["mixed"]["value"] /
+                                                                    sp_lines["fp64"]["value"], 3)
+    if "mixed" in sp_conv and "fp64" in sp_conv:
+        line["film_2048_spectral"]["mixed_over_fp64_converged"] = round(sp_conv["mixed"]["value"] /
+                                                                        sp_conv["fp64"]["value"], 3)
     # the film with a circular hole of Sec. 2.3, Fig. 3 (768 x 512, radix-12 row transforms)
     if not a.quick:
         line["film_768x512_hole"] = hole_film_lines(a)
