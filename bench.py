@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--t", type=float, default=0.6, help="snapshot time")
     ap.add_argument("--iters", type=int, default=4, help="inner iterations per right-hand side")
     ap.add_argument("--window", type=int, default=20, help="timed BS23 attempts of the converged line")
+    ap.add_argument("--only-hole", action="store_true",
+                    help="only the 768x512 film with a hole (Sec. 2.3, Fig. 3), e.g. for a kernel trace")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 64 MiB read + 64 MiB write kernel 3 times (counter calibration)")
     return ap.parse_args()
@@ -650,6 +652,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.only_hole:
+        print(json.dumps(dict(film_768x512_hole=hole_film_lines(a))), flush=True)
+        return
     masks = [a.mask] if a.quick else [a.mask] + [m for m in ("ring", "slot") if m != a.mask]
     precs = [a.quick_prec] if a.quick else ["mixed", "fp64", "final64"]
     hp = precs[0]   # precision of the roofline and kernel-table lines
