@@ -606,7 +606,7 @@ def kernel_table(prof, n, kx, ny, prec, iters, n_out):
     return rows
 
 
-def accuracy(wl):
+def accuracy(wl, deriv="staggered"):
     """Error of the two mixed forms per result: a ring film of the workload's
     structure at ACC_N^2 (same field, law, rho_out and jc statistics)
     integrated from the virgin state to ACC_T_END by the adaptive FP64 form
@@ -622,7 +622,7 @@ def accuracy(wl):
     jc = W.lognormal_jc((ACC_N, ACC_N), wl["jc"]["s"], wl["jc"]["ell"], wl["jc"]["seed"])
     state = torch.zeros((ACC_N, ACC_N), dtype=torch.float64, device="cuda")
     forms = ("mixed", "final64")
-    ctx = {p: make_ctx(p, w, mat, jc, 0) for p in ("fp64",) + forms}
+    ctx = {p: make_ctx(p, w, mat, jc, 0, deriv=deriv) for p in ("fp64",) + forms}
     for c in ctx.values():
         c.set_warm_start(False)
     grid = step_grid(ctx["fp64"], state, 0.0, ACC_T_END)
@@ -636,8 +636,8 @@ def accuracy(wl):
         c.close()
     out["rhs_at_end"] = {p: (torch.linalg.norm(o[p] - o["fp64"]) / torch.linalg.norm(o["fp64"])).item()
                          for p in forms}
-    out["after"] = ("%d^2 ring film (workload structure) from the virgin state, %d adaptive BS23 steps to "
-                    "t = %.4g, converged inner iteration" % (ACC_N, len(grid), t_end))
+    out["after"] = ("%d^2 ring film (workload structure, %s form) from the virgin state, %d adaptive BS23 steps "
+                    "to t = %.4g, converged inner iteration" % (ACC_N, deriv, len(grid), t_end))
     return out
 
 
@@ -754,6 +754,8 @@ def main():
     if "mixed" in sp_conv and "fp64" in sp_conv:
         line["film_2048_spectral"]["mixed_over_fp64_converged"] = round(sp_conv["mixed"]["value"] /
                                                                         sp_conv["fp64"]["value"], 3)
+    if not a.quick:
+        line["film_2048_spectral"]["mixed_vs_fp64_per_result"] = accuracy(wl, deriv="spectral")
     # the film with a circular hole of Sec. 2.3, Fig. 3 (768 x 512, radix-12 row transforms)
     if not a.quick:
         line["film_768x512_hole"] = hole_film_lines(a)
